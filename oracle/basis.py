@@ -1,0 +1,144 @@
+"""M-scheme basis of the oracle (test infrastructure; see package docstring).
+
+Follows the paper's Sec. 2 (Slater determinants as bit strings, Eq. for
+|M_i>) and App. A (Table 1 ordering, partitions Gamma = (N^p, N^n, M^p) and the
+product form |M_i> = |p_i> (x) |n_i>).
+
+Readings (the paper fixes them only through Table 1):
+  * m-states: orbit order as given, then 2m ascending; bit s is state s.
+  * species sector order: occupation partitions in descending lexicographic
+    order; inside a partition, occupied-state tuples in ascending
+    lexicographic order. Table 1 is exactly this for d5/2 + s1/2.
+  * product basis: blocks by 2M_p ascending, then proton parity + before -,
+    then neutron parity + before -; inside a block proton-major:
+    index = offset + p * D_n + n.
+"""
+from __future__ import annotations
+
+import itertools
+from dataclasses import dataclass
+
+
+def m_states(orbits):
+    """[(orbit index, 2m)] in orbit order, 2m ascending."""
+    out = []
+    for k, (_n, _l, twoj) in enumerate(orbits):
+        for twom in range(-twoj, twoj + 1, 2):
+            out.append((k, twom))
+    return out
+
+
+def species_sectors(orbits, n_part):
+    """All SDs of ``n_part`` identical nucleons keyed by (2M, parity).
+
+    Each value is a list of (bitmask, partition) in Table-1 order.
+    """
+    states = m_states(orbits)
+    norb = len(orbits)
+    sectors = {}
+    for occ in itertools.combinations(range(len(states)), n_part):
+        twoM = sum(states[s][1] for s in occ)
+        par = 1
+        part = [0] * norb
+        for s in occ:
+            part[states[s][0]] += 1
+            if orbits[states[s][0]][1] % 2:
+                par = -par
+        key = (twoM, par)
+        sectors.setdefault(key, []).append((tuple(-x for x in part), occ))
+    out = {}
+    for key, lst in sectors.items():
+        lst.sort()
+        out[key] = [(sum(1 << s for s in occ), tuple(-x for x in negpart)) for negpart, occ in lst]
+    return out
+
+
+@dataclass
+class Block:
+    twoMp: int
+    parp: int
+    twoMn: int
+    parn: int
+    dp: int
+    dn: int
+    offset: int
+
+
+class ProductBasis:
+    """Proton x neutron M-scheme basis for fixed 2M (and optionally parity)."""
+
+    def __init__(self, orbits, n_prot, n_neut, twoM, parity=0):
+        self.orbits = tuple(orbits)
+        self.nstates = len(m_states(orbits))
+        self.n_prot, self.n_neut, self.twoM, self.parity = n_prot, n_neut, twoM, parity
+        self.psec = species_sectors(orbits, n_prot)
+        self.nsec = species_sectors(orbits, n_neut)
+        keys = []
+        for (tmp, pp) in self.psec:
+            for (tmn, pn) in self.nsec:
+                if tmp + tmn != twoM:
+                    continue
+                if parity != 0 and pp * pn != parity:
+                    continue
+                keys.append((tmp, -pp, -pn, tmn, pp, pn))
+        keys.sort()
+        self.blocks = []
+        off = 0
+        for tmp, _a, _b, tmn, pp, pn in keys:
+            dp, dn = len(self.psec[(tmp, pp)]), len(self.nsec[(tmn, pn)])
+            self.blocks.append(Block(tmp, pp, tmn, pn, dp, dn, off))
+            off += dp * dn
+        self.dim = off
+
+    def states(self):
+        """(proton bitmask, neutron bitmask) for every basis index, in order."""
+        out = []
+        for b in self.blocks:
+            plist = self.psec[(b.twoMp, b.parp)]
+            nlist = self.nsec[(b.twoMn, b.parn)]
+            for pw, _ in plist:
+                for nw, _ in nlist:
+                    out.append((pw, nw))
+        return out
+
+    def combined_words(self):
+        """One word per basis state: proton bits low, neutron bits shifted by the state count."""
+        ns = self.nstates
+        return [pw | (nw << ns) for pw, nw in self.states()]
+
+
+def count_sds(orbits, n_part):
+    """Number of SDs by (2M, parity) for ``n_part`` nucleons, by dynamic programming over orbits.
+
+    Independent of the enumeration in ``species_sectors``: each orbit contributes
+    subsets of its own m-states, and the counts are convolved orbit by orbit.
+    """
+    table = {(0, 0, 1): 1}  # (particles, 2M, parity) -> count
+    for (_n, l, twoj) in orbits:
+        ms = list(range(-twoj, twoj + 1, 2))
+        orb = {}
+        for k in range(len(ms) + 1):
+            for sub in itertools.combinations(ms, k):
+                key = (k, sum(sub))
+                orb[key] = orb.get(key, 0) + 1
+        new = {}
+        for (n0, m0, p0), c0 in table.items():
+            for (k, m), c in orb.items():
+                if n0 + k > n_part:
+                    continue
+                key = (n0 + k, m0 + m, p0 * ((-1) ** (l * k)))
+                new[key] = new.get(key, 0) + c0 * c
+        table = new
+    return {(m, p): c for (n, m, p), c in table.items() if n == n_part}
+
+
+def count_dim(orbits_p, n_prot, orbits_n, n_neut, twoM, parity=0):
+    """M-scheme dimension from per-species DP counts (no enumeration)."""
+    cp = count_sds(orbits_p, n_prot) if n_prot or orbits_p else {(0, 1): 1}
+    cn = count_sds(orbits_n, n_neut) if n_neut or orbits_n else {(0, 1): 1}
+    tot = 0
+    for (mp, pp), a in cp.items():
+        for (mn, pn), b in cn.items():
+            if mp + mn == twoM and (parity == 0 or pp * pn == parity):
+                tot += a * b
+    return tot
