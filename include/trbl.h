@@ -1,0 +1,141 @@
+/*
+ * trbl.h -- C ABI of libtrbl: thick-restart block Lanczos (TRBL) for the
+ * M-scheme nuclear shell model on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Shimizu, Mizusaki, Utsuno, Tsunoda, "Thick-restart block Lanczos
+ * method for large-scale shell-model calculations" (arXiv:1902.02064).
+ *   - model space and basis: Sec. 2 (M-scheme Slater determinants as bit
+ *     strings) and App. A (Table 1 ordering, partitions, proton x neutron
+ *     product form);
+ *   - Hamiltonian: Sec. 2 (one-body + two-body operator with J-coupled
+ *     two-body matrix elements);
+ *   - H applied to a block of vectors on the fly: App. B (identical-particle
+ *     two-body jumps; proton-neutron factorisation through one-body jumps);
+ *   - eigensolver: Alg. 4 and the thick-restart equations of Sec. 3.4.
+ *
+ * Conventions (fixed by this header):
+ *   - Single-particle m-states of one species: orbits in the order given,
+ *     then 2m ascending (Table 1 column order); bit s of a 64-bit word is
+ *     state s. At most 64 m-states per species.
+ *   - Species sectors (2M_s, parity): occupation partitions in descending
+ *     lexicographic order; inside a partition, occupied-state tuples in
+ *     ascending lexicographic order (this is exactly Table 1).
+ *   - Product basis: blocks ordered by 2M_p ascending, then proton parity
+ *     + before -, then neutron parity + before -; inside a block,
+ *     index = block offset + p * D_n + n  (proton-major).
+ *   - Vectors: row-major [D][nb] (element (i, c) at i*nb + c), FP64
+ *     (TRBL_FP64) or FP32 (TRBL_MIXED), caller-owned device memory.
+ *   - Two-body matrix elements: proton-neutron formalism, normalised and
+ *     antisymmetrised J-coupled elements V_J(ab,cd) with Condon-Shortley
+ *     Clebsch-Gordan coefficients, orbit a coupled before b (proton before
+ *     neutron in the pn channel). Each independent element is listed once;
+ *     the mirror V_J(cd,ab) is implied. An identical-particle pair given as
+ *     (b,a) is reordered with V_J(ba,cd) = -(-1)^(ja+jb-J) V_J(ab,cd).
+ *
+ * Errors: every int-returning call returns 0 on success, a negative
+ * TRBL_E* code on failure (message from trbl_last_error(), thread-local),
+ * or TRBL_NOT_CONVERGED (+1) from trbl_solve, which still writes the best
+ * Ritz pairs. No C++ exception crosses this boundary.
+ * Threading: one model may be used by one host thread / stream at a time.
+ */
+#ifndef TRBL_H
+#define TRBL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TRBL_OK 0
+#define TRBL_NOT_CONVERGED 1
+#define TRBL_E_INVALID (-1)   /* bad argument */
+#define TRBL_E_EMPTY (-2)     /* empty model space (D = 0) */
+#define TRBL_E_TOO_MANY (-3)  /* more than 64 m-states per species */
+#define TRBL_E_NOMEM (-4)     /* host or device allocation failed */
+#define TRBL_E_DEVICE (-5)    /* HIP runtime error */
+#define TRBL_E_BREAKDOWN (-6) /* unrecoverable Lanczos breakdown */
+#define TRBL_E_STATE (-7)     /* call order (e.g. no Hamiltonian set) */
+
+typedef struct trbl_model trbl_model; /* opaque, library-owned */
+
+typedef enum { TRBL_FP64 = 0, TRBL_MIXED = 1 } trbl_precision;
+
+typedef struct {
+  int n, l, twoj; /* radial number, orbital l, 2j */
+} trbl_orbit;
+
+typedef struct {
+  int channel;    /* 0 = pp, 1 = nn, 2 = pn (a, c proton orbits; b, d neutron orbits) */
+  int a, b, c, d; /* orbit indices into the model's orbit list */
+  int twoJ;       /* 2J of the pair */
+  double v;       /* V_J(ab,cd) */
+} trbl_tbme;
+
+typedef struct {
+  int nb;          /* block size p (1..64) */
+  int n_eig;       /* wanted lowest eigenpairs N */
+  int l_s;         /* vectors kept at a thick restart (N <= l_s) */
+  int l_m;         /* maximum stored Lanczos vectors (l_s + 2*nb <= l_m <= D) */
+  int max_iter;    /* block iterations before giving up */
+  double tol;      /* residual tolerance: rho_i <= tol * max|theta| */
+  int precision;   /* trbl_precision */
+  int refine;      /* mixed mode: 1 = final FP64 Rayleigh-Ritz refinement */
+  uint64_t seed;   /* seed of the random start block (splitmix64 + Box-Muller) */
+  const void* v0;  /* optional device start block [D][nb] (FP64 or FP32 per precision); NULL = random */
+  void* stream;    /* hipStream_t; NULL = default stream */
+} trbl_opts;
+
+typedef struct {
+  int iterations, restarts, n_converged, breakdowns;
+  double t_total, t_hv, t_orth, t_qr, t_eig, t_restart, t_refine; /* seconds (device events) */
+  double* resid;   /* optional caller host buffer of n_eig residual norms */
+} trbl_info;
+
+/* Build the M-scheme product basis (Sec. 2, App. A). parity: +1, -1, or 0 for both.
+   Copies the orbit list. *out owns host and device tables until trbl_model_destroy. */
+int trbl_model_create(const trbl_orbit* orbits, int n_orbits, int n_prot, int n_neut, int twoM,
+                      int parity, trbl_model** out);
+void trbl_model_destroy(trbl_model* m);
+
+/* M-scheme dimension D. */
+int trbl_model_dim(const trbl_model* m, int64_t* dim);
+
+/* Host-side index <-> bit strings (App. A, Table 1 order). rank writes -1 for a state outside the basis. */
+int trbl_basis_unrank(const trbl_model* m, int64_t i, uint64_t* pbits, uint64_t* nbits);
+int trbl_basis_rank(const trbl_model* m, uint64_t pbits, uint64_t nbits, int64_t* i);
+
+/* Device-side bulk versions (GPU kernels): idx, pbits, nbits are device arrays of length n. */
+int trbl_basis_unrank_dev(const trbl_model* m, const int64_t* idx, int64_t n, uint64_t* pbits,
+                          uint64_t* nbits, void* stream);
+int trbl_basis_rank_dev(const trbl_model* m, const uint64_t* pbits, const uint64_t* nbits, int64_t n,
+                        int64_t* idx, void* stream);
+
+/* Set H = sum_a e_a n_a + two-body (Sec. 2). spe_p, spe_n: one energy per orbit (host).
+   tbme: n_v host elements. Copies everything, builds the one-body jump and
+   identical-particle tables of App. B on the device. */
+int trbl_set_hamiltonian(trbl_model* m, const double* spe_p, const double* spe_n, const trbl_tbme* tbme,
+                         int64_t n_v);
+
+/* W = H V for a block of nb vectors (App. B, on-the-fly block H.V). V, W: device [D][nb],
+   FP64 if precision == TRBL_FP64, FP32 (FP32 accumulation) if TRBL_MIXED. V and W must not alias. */
+int trbl_apply(const trbl_model* m, int precision, int nb, const void* V, void* W, void* stream);
+
+/* Lowest n_eig eigenpairs by TRBL (Alg. 4, Sec. 3.4). evals: host n_eig doubles (ascending).
+   evecs: optional device [D][n_eig] FP64 Ritz vectors (orthonormal columns). info: optional. */
+int trbl_solve(const trbl_model* m, const trbl_opts* opts, double* evals, void* evecs, trbl_info* info);
+
+/* Gradient of sum_k w_k E_k (Hellmann-Feynman) with respect to every element of the last
+   trbl_set_hamiltonian list (grad_v, host n_v) and optionally the proton then neutron
+   single-particle energies (grad_spe, host 2*n_orbits, may be NULL).
+   evecs: device [D][n_eig] FP64 eigenvectors; NULL = recompute them with trbl_solve(opts). */
+int trbl_tbme_grad(const trbl_model* m, const trbl_opts* opts, int n_eig, const double* w,
+                   const void* evecs, double* grad_v, double* grad_spe);
+
+/* Message of the last failing call on this thread. */
+const char* trbl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TRBL_H */

@@ -1,0 +1,248 @@
+"""Python binding of libtrbl (thick-restart block Lanczos shell-model eigensolver on MI355X).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libtrbl.so`` behind the C ABI declared in ``include/trbl.h``.
+PyTorch supplies device memory and the current HIP stream. There is no CPU
+fallback: if the library is missing, loading fails with an error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtrbl.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "trbl.h")
+
+TRBL_FP64, TRBL_MIXED = 0, 1
+TRBL_NOT_CONVERGED = 1
+
+
+class TrblError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libtrbl error {code}: {msg}")
+        self.code = code
+
+
+class Orbit(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("l", ctypes.c_int), ("twoj", ctypes.c_int)]
+
+
+class Tbme(ctypes.Structure):
+    _fields_ = [("channel", ctypes.c_int), ("a", ctypes.c_int), ("b", ctypes.c_int), ("c", ctypes.c_int),
+                ("d", ctypes.c_int), ("twoJ", ctypes.c_int), ("v", ctypes.c_double)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("nb", ctypes.c_int), ("n_eig", ctypes.c_int), ("l_s", ctypes.c_int), ("l_m", ctypes.c_int),
+                ("max_iter", ctypes.c_int), ("tol", ctypes.c_double), ("precision", ctypes.c_int),
+                ("refine", ctypes.c_int), ("seed", ctypes.c_uint64), ("v0", ctypes.c_void_p),
+                ("stream", ctypes.c_void_p)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("n_converged", ctypes.c_int),
+                ("breakdowns", ctypes.c_int), ("t_total", ctypes.c_double), ("t_hv", ctypes.c_double),
+                ("t_orth", ctypes.c_double), ("t_qr", ctypes.c_double), ("t_eig", ctypes.c_double),
+                ("t_restart", ctypes.c_double), ("t_refine", ctypes.c_double),
+                ("resid", ctypes.POINTER(ctypes.c_double))]
+
+
+_lib = None
+
+
+def load():
+    """Load libtrbl.so (built by ``build.py``); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} not built; run paper_1902_02064_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, I64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+    sig = {
+        "trbl_model_create": ([ctypes.POINTER(Orbit), I, I, I, I, I, ctypes.POINTER(P)], I),
+        "trbl_model_destroy": ([P], None),
+        "trbl_model_dim": ([P, ctypes.POINTER(I64)], I),
+        "trbl_basis_unrank": ([P, I64, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)], I),
+        "trbl_basis_rank": ([P, ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(I64)], I),
+        "trbl_basis_unrank_dev": ([P, P, I64, P, P, P], I),
+        "trbl_basis_rank_dev": ([P, P, P, I64, P, P], I),
+        "trbl_set_hamiltonian": ([P, P, P, ctypes.POINTER(Tbme), I64], I),
+        "trbl_apply": ([P, I, I, P, P, P], I),
+        "trbl_solve": ([P, ctypes.POINTER(Opts), P, P, ctypes.POINTER(Info)], I),
+        "trbl_tbme_grad": ([P, ctypes.POINTER(Opts), I, P, P, P, P], I),
+        "trbl_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def header_symbols():
+    """Names of the functions declared in include/trbl.h."""
+    import re
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(trbl_[a-z_]+)\s*\(", text)))
+
+
+def _check(rc):
+    if rc < 0:
+        raise TrblError(rc, load().trbl_last_error().decode())
+    return rc
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class SolveInfo:
+    iterations: int
+    restarts: int
+    n_converged: int
+    breakdowns: int
+    t_total: float
+    t_hv: float
+    t_orth: float
+    t_qr: float
+    t_eig: float
+    t_restart: float
+    t_refine: float
+    resid: np.ndarray
+    converged: bool
+
+
+class Model:
+    """M-scheme model space (Sec. 2, App. A) with its Hamiltonian, on the current HIP device."""
+
+    def __init__(self, orbits, n_prot, n_neut, twoM, parity=0):
+        lib = load()
+        arr = (Orbit * len(orbits))(*[Orbit(*o) for o in orbits])
+        h = ctypes.c_void_p()
+        _check(lib.trbl_model_create(arr, len(orbits), n_prot, n_neut, twoM, parity, ctypes.byref(h)))
+        self._h = h
+        self.orbits = tuple(tuple(o) for o in orbits)
+        d = ctypes.c_int64()
+        _check(lib.trbl_model_dim(h, ctypes.byref(d)))
+        self.dim = int(d.value)
+        self.n_tbme = 0
+
+    def close(self):
+        if self._h:
+            load().trbl_model_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- basis
+    def unrank(self, i):
+        p, n = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(load().trbl_basis_unrank(self._h, int(i), ctypes.byref(p), ctypes.byref(n)))
+        return int(p.value), int(n.value)
+
+    def rank(self, pbits, nbits):
+        i = ctypes.c_int64()
+        _check(load().trbl_basis_rank(self._h, int(pbits), int(nbits), ctypes.byref(i)))
+        return int(i.value)
+
+    def unrank_dev(self, idx):
+        import torch
+        idx = idx.to(torch.int64).contiguous()
+        p = torch.empty_like(idx)
+        n = torch.empty_like(idx)
+        _check(load().trbl_basis_unrank_dev(self._h, _ptr(idx), idx.numel(), _ptr(p), _ptr(n), _stream()))
+        return p, n
+
+    def rank_dev(self, pbits, nbits):
+        import torch
+        pbits = pbits.to(torch.int64).contiguous()
+        nbits = nbits.to(torch.int64).contiguous()
+        out = torch.empty_like(pbits)
+        _check(load().trbl_basis_rank_dev(self._h, _ptr(pbits), _ptr(nbits), pbits.numel(), _ptr(out),
+                                          _stream()))
+        return out
+
+    # -- Hamiltonian
+    def set_hamiltonian(self, spe_p, spe_n, tbme):
+        norb = len(self.orbits)
+        sp = (ctypes.c_double * norb)(*[float(x) for x in spe_p[:norb]])
+        sn = (ctypes.c_double * norb)(*[float(x) for x in spe_n[:norb]])
+        arr = (Tbme * max(1, len(tbme)))(*[Tbme(int(t[0]), int(t[1]), int(t[2]), int(t[3]), int(t[4]),
+                                                 int(t[5]), float(t[6])) for t in tbme])
+        _check(load().trbl_set_hamiltonian(self._h, sp, sn, arr, len(tbme)))
+        self.n_tbme = len(tbme)
+
+    def apply(self, V, W=None):
+        """W = H V on the device; V is [D, nb] float64 (FP64) or float32 (mixed precision)."""
+        import torch
+        assert V.is_cuda and V.dim() == 2 and V.shape[0] == self.dim and V.is_contiguous()
+        prec = TRBL_FP64 if V.dtype == torch.float64 else TRBL_MIXED
+        if V.dtype not in (torch.float64, torch.float32):
+            raise TypeError("V must be float64 or float32")
+        if W is None:
+            W = torch.empty_like(V)
+        assert W.shape == V.shape and W.dtype == V.dtype and W.is_contiguous()
+        _check(load().trbl_apply(self._h, prec, V.shape[1], _ptr(V), _ptr(W), _stream()))
+        return W
+
+    # -- eigensolver
+    def _opts(self, nb, n_eig, l_s, l_m, tol, precision, max_iter, seed, v0, refine):
+        o = Opts()
+        o.nb, o.n_eig, o.l_s, o.l_m, o.max_iter = nb, n_eig, l_s, l_m, max_iter
+        o.tol = tol
+        o.precision = TRBL_FP64 if precision == "fp64" else TRBL_MIXED
+        o.refine = 1 if refine else 0
+        o.seed = seed
+        o.v0 = None if v0 is None else v0.data_ptr()
+        o.stream = _stream().value
+        return o
+
+    def solve(self, nb, n_eig, l_s, l_m, tol, precision="fp64", max_iter=5000, seed=1000, v0=None,
+              refine=True, vectors=False):
+        """Lowest eigenpairs by TRBL (Alg. 4). Returns (evals, evecs or None, SolveInfo)."""
+        import torch
+        o = self._opts(nb, n_eig, l_s, l_m, tol, precision, max_iter, seed, v0, refine)
+        ev = (ctypes.c_double * n_eig)()
+        res = (ctypes.c_double * n_eig)()
+        info = Info()
+        info.resid = ctypes.cast(res, ctypes.POINTER(ctypes.c_double))
+        X = torch.empty((self.dim, n_eig), dtype=torch.float64, device="cuda") if vectors else None
+        rc = _check(load().trbl_solve(self._h, ctypes.byref(o), ev, None if X is None else _ptr(X),
+                                      ctypes.byref(info)))
+        si = SolveInfo(info.iterations, info.restarts, info.n_converged, info.breakdowns, info.t_total,
+                       info.t_hv, info.t_orth, info.t_qr, info.t_eig, info.t_restart, info.t_refine,
+                       np.array(res[:]), rc == 0)
+        return np.array(ev[:]), X, si
+
+    def tbme_grad(self, weights, evecs=None, nb=8, l_s=None, l_m=None, tol=1e-10, max_iter=5000, seed=1000,
+                  spe=True):
+        """d(sum_k w_k E_k)/dV for every element given to set_hamiltonian (and the spe if asked)."""
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        n = len(w)
+        l_s = l_s or max(2 * n, n + nb)
+        l_m = l_m or min(self.dim, l_s + 6 * nb)
+        o = self._opts(nb, n, l_s, l_m, tol, "fp64", max_iter, seed, None, True)
+        gv = np.zeros(max(1, self.n_tbme))
+        gs = np.zeros(2 * len(self.orbits)) if spe else None
+        _check(load().trbl_tbme_grad(self._h, ctypes.byref(o), n, w.ctypes.data_as(ctypes.c_void_p),
+                                     None if evecs is None else _ptr(evecs),
+                                     gv.ctypes.data_as(ctypes.c_void_p),
+                                     None if gs is None else gs.ctypes.data_as(ctypes.c_void_p)))
+        return gv[:self.n_tbme], gs

@@ -1,0 +1,179 @@
+// C ABI of libtrbl (declared in include/trbl.h): argument checks, error
+// capture, and dispatch to the host set-up, the H.V kernels and the solver.
+#include <cstring>
+
+#include "internal.h"
+
+namespace trbl {
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace trbl
+
+using trbl::Error;
+
+template <class F>
+static int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    trbl::set_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    trbl::set_error("host allocation failed");
+    return TRBL_E_NOMEM;
+  } catch (const std::exception& e) {
+    trbl::set_error(e.what());
+    return TRBL_E_INVALID;
+  } catch (...) {
+    trbl::set_error("unknown error");
+    return TRBL_E_INVALID;
+  }
+}
+
+extern "C" {
+
+const char* trbl_last_error(void) { return trbl::g_last_error.c_str(); }
+
+int trbl_model_create(const trbl_orbit* orbits, int n_orbits, int n_prot, int n_neut, int twoM, int parity,
+                      trbl_model** out) {
+  return guarded([&] {
+    TRBL_REQUIRE(out != nullptr, TRBL_E_INVALID, "out is NULL");
+    *out = nullptr;
+    auto* h = new trbl_model();
+    try {
+      TRBL_HIP(hipGetDevice(&h->m.device));
+      trbl::build_model(h->m, orbits, n_orbits, n_prot, n_neut, twoM, parity);
+    } catch (...) {
+      delete h;
+      throw;
+    }
+    *out = h;
+    return TRBL_OK;
+  });
+}
+
+void trbl_model_destroy(trbl_model* m) { delete m; }
+
+int trbl_model_dim(const trbl_model* m, int64_t* dim) {
+  return guarded([&] {
+    TRBL_REQUIRE(m && dim, TRBL_E_INVALID, "NULL argument");
+    *dim = m->m.dim;
+    return TRBL_OK;
+  });
+}
+
+int trbl_basis_unrank(const trbl_model* h, int64_t i, uint64_t* pbits, uint64_t* nbits) {
+  return guarded([&] {
+    TRBL_REQUIRE(h && pbits && nbits, TRBL_E_INVALID, "NULL argument");
+    const trbl::Model& m = h->m;
+    TRBL_REQUIRE(i >= 0 && i < m.dim, TRBL_E_INVALID, "index out of range");
+    size_t lo = 0, hi = m.blocks.size() - 1;
+    while (lo < hi) {
+      size_t mid = (lo + hi + 1) / 2;
+      if (m.blocks[mid].off <= i) lo = mid;
+      else hi = mid - 1;
+    }
+    const auto& b = m.blocks[lo];
+    int64_t rel = i - b.off;
+    *pbits = m.sp[0].words[m.sp[0].sectors[b.psec].start + rel / b.dn];
+    *nbits = m.sp[1].words[m.sp[1].sectors[b.nsec].start + rel % b.dn];
+    return TRBL_OK;
+  });
+}
+
+int trbl_basis_rank(const trbl_model* h, uint64_t pbits, uint64_t nbits, int64_t* i) {
+  return guarded([&] {
+    TRBL_REQUIRE(h && i, TRBL_E_INVALID, "NULL argument");
+    const trbl::Model& m = h->m;
+    *i = -1;
+    auto ip = m.sp[0].index.find(pbits);
+    auto in = m.sp[1].index.find(nbits);
+    if (ip == m.sp[0].index.end() || in == m.sp[1].index.end()) return TRBL_OK;
+    int kp = m.sp[0].sector_of[ip->second], kn = m.sp[1].sector_of[in->second];
+    for (const auto& b : m.blocks)
+      if (b.psec == kp && b.nsec == kn) {
+        *i = b.off + (int64_t)(ip->second - m.sp[0].sectors[kp].start) * b.dn +
+             (in->second - m.sp[1].sectors[kn].start);
+        break;
+      }
+    return TRBL_OK;
+  });
+}
+
+int trbl_basis_unrank_dev(const trbl_model* h, const int64_t* idx, int64_t n, uint64_t* pbits, uint64_t* nbits,
+                          void* stream) {
+  return guarded([&] {
+    TRBL_REQUIRE(h && (n == 0 || (idx && pbits && nbits)) && n >= 0, TRBL_E_INVALID, "bad argument");
+    trbl::launch_unrank(h->m, idx, n, pbits, nbits, (hipStream_t)stream);
+    return TRBL_OK;
+  });
+}
+
+int trbl_basis_rank_dev(const trbl_model* h, const uint64_t* pbits, const uint64_t* nbits, int64_t n, int64_t* idx,
+                        void* stream) {
+  return guarded([&] {
+    TRBL_REQUIRE(h && (n == 0 || (idx && pbits && nbits)) && n >= 0, TRBL_E_INVALID, "bad argument");
+    trbl::launch_rank(h->m, pbits, nbits, n, idx, (hipStream_t)stream);
+    return TRBL_OK;
+  });
+}
+
+int trbl_set_hamiltonian(trbl_model* h, const double* spe_p, const double* spe_n, const trbl_tbme* tbme,
+                         int64_t n_v) {
+  return guarded([&] {
+    TRBL_REQUIRE(h != nullptr, TRBL_E_INVALID, "NULL model");
+    trbl::build_hamiltonian(h->m, spe_p, spe_n, tbme, n_v);
+    return TRBL_OK;
+  });
+}
+
+int trbl_apply(const trbl_model* h, int precision, int nb, const void* V, void* W, void* stream) {
+  return guarded([&] {
+    TRBL_REQUIRE(h != nullptr, TRBL_E_INVALID, "NULL model");
+    TRBL_REQUIRE(precision == TRBL_FP64 || precision == TRBL_MIXED, TRBL_E_INVALID, "bad precision");
+    trbl::launch_apply(h->m, precision, nb, V, nb, W, nb, (hipStream_t)stream);
+    return TRBL_OK;
+  });
+}
+
+int trbl_solve(const trbl_model* h, const trbl_opts* opts, double* evals, void* evecs, trbl_info* info) {
+  return guarded([&] {
+    TRBL_REQUIRE(h && opts && evals, TRBL_E_INVALID, "NULL argument");
+    return trbl::solve(h->m, *opts, evals, evecs, info);
+  });
+}
+
+int trbl_tbme_grad(const trbl_model* h, const trbl_opts* opts, int n_eig, const double* w, const void* evecs,
+                   double* grad_v, double* grad_spe) {
+  return guarded([&] {
+    TRBL_REQUIRE(h && w && grad_v && n_eig > 0, TRBL_E_INVALID, "bad argument");
+    const trbl::Model& m = h->m;
+    TRBL_REQUIRE(m.has_h, TRBL_E_STATE, "no Hamiltonian set");
+    hipStream_t s = opts ? (hipStream_t)opts->stream : nullptr;
+    trbl::DevBuf own;
+    const double* X = static_cast<const double*>(evecs);
+    if (!X) {
+      TRBL_REQUIRE(opts != nullptr, TRBL_E_INVALID, "opts needed to recompute eigenvectors");
+      TRBL_REQUIRE(opts->n_eig >= n_eig, TRBL_E_INVALID, "opts.n_eig smaller than n_eig");
+      own.alloc((size_t)m.dim * opts->n_eig * sizeof(double));
+      std::vector<double> ev(opts->n_eig);
+      int rc = trbl::solve(m, *opts, ev.data(), own.p, nullptr);
+      TRBL_REQUIRE(rc == TRBL_OK, rc < 0 ? rc : TRBL_E_BREAKDOWN, "eigenvector recomputation did not converge");
+      // keep the n_eig lowest columns: [D][opts.n_eig] -> strided use below
+      if (opts->n_eig != n_eig) {
+        trbl::DevBuf tight;
+        tight.alloc((size_t)m.dim * n_eig * sizeof(double));
+        TRBL_HIP(hipMemcpy2DAsync(tight.p, n_eig * sizeof(double), own.p, opts->n_eig * sizeof(double),
+                                  n_eig * sizeof(double), (size_t)m.dim, hipMemcpyDeviceToDevice, s));
+        TRBL_HIP(hipStreamSynchronize(s));
+        std::swap(own.p, tight.p);
+        std::swap(own.bytes, tight.bytes);
+      }
+      X = own.as<double>();
+    }
+    trbl::tbme_gradient(m, n_eig, w, X, grad_v, grad_spe, s);
+    return TRBL_OK;
+  });
+}
+
+}  // extern "C"

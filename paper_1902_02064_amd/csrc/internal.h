@@ -1,0 +1,167 @@
+// Internal declarations shared by the host and device parts of libtrbl.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/trbl.h"
+
+namespace trbl {
+
+// ---------------------------------------------------------------- errors
+struct Error {
+  int code;
+  std::string msg;
+};
+void set_error(const std::string& msg);
+#define TRBL_HIP(call)                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      throw ::trbl::Error{TRBL_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+#define TRBL_REQUIRE(cond, code, msg)                     \
+  do {                                                    \
+    if (!(cond)) throw ::trbl::Error{(code), (msg)};      \
+  } while (0)
+
+// ---------------------------------------------------------------- device buffer
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(size_t n) {
+    if (n <= bytes && p) return;
+    release();
+    if (n == 0) n = 8;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+      p = nullptr;
+      throw Error{TRBL_E_NOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed"};
+    }
+    bytes = n;
+  }
+  template <class T>
+  void upload(const std::vector<T>& v) {
+    alloc(v.size() * sizeof(T));
+    if (!v.empty()) TRBL_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// ---------------------------------------------------------------- model
+struct SpeciesSector {
+  int twoM, par;
+  int start, size;  // global species index range
+};
+
+struct Species {
+  int npart = 0;
+  std::vector<uint64_t> words;                 // all SDs, sector by sector
+  std::vector<int> sector_of;                  // global index -> sector id
+  std::vector<SpeciesSector> sectors;          // ordered by (2M asc, parity + first)
+  std::unordered_map<uint64_t, int> index;     // word -> global index
+  std::vector<uint64_t> part_key;              // per SD: partition key (for device ranking)
+};
+
+struct BlockInfo {
+  int psec, nsec;  // species sector ids
+  int dp, dn;
+  int64_t off;
+};
+
+// One-body jump classes: change of 2M (in steps of 2) and parity flip.
+struct Classes {
+  int tjmax = 0;   // largest 2j
+  int nclass = 0;  // (2*tjmax+1) * 2
+  int cls(int d2, int flip) const { return ((d2 + 2 * tjmax) / 2) * 2 + flip; }
+  int conj(int c) const {  // class of the opposite-species jump: -d2, same flip
+    int di = c / 2, f = c % 2;
+    return (2 * tjmax - di) * 2 + f;
+  }
+};
+
+struct DeviceTables {
+  // blocks
+  DevBuf blk_dp, blk_dn, blk_off, blk_p0, blk_n0, blk_item0, src_blk;
+  // species words and sector info (for rank/unrank)
+  DevBuf pwords, nwords, ppart, npart, psec_start, psec_size, nsec_start, nsec_size, blk_of_sec;
+  DevBuf psec_tm, psec_par, nsec_tm, nsec_par;
+  // jumps
+  DevBuf pj_start, pj_idx, pj_meta, nj_start, nj_idx, nj_meta;
+  DevBuf h_off, h_ncol, h64, h32;
+  DevBuf pp_ptr, pp_col, pp_v64, pp_v32, nn_ptr, nn_col, nn_v64, nn_v32;
+  // gradient bins: per identical-particle operator entry / pn op pair, which m-scheme term
+  DevBuf pp_term, nn_term;  // per CSR entry: list range into term lists
+  DevBuf pp_tptr, pp_tid, pp_tsgn, nn_tptr, nn_tid, nn_tsgn;
+  DevBuf h_term;            // per pn table entry: m-scheme pn term id (-1 if none)
+};
+
+struct MTerm {  // m-scheme two-body term c+_a c+_b c_d c_c (species-local state indices)
+  int a, b, c, d;
+  double h;
+};
+
+struct Model {
+  // space
+  std::vector<trbl_orbit> orbits;
+  int ns = 0;                      // m-states per species
+  std::vector<int> st_orb, st_tm;  // per m-state: orbit, 2m
+  int n_prot = 0, n_neut = 0, twoM = 0, parity = 0;
+  Species sp[2];
+  std::vector<BlockInfo> blocks;
+  int64_t dim = 0;
+  Classes cl;
+  int device = 0;
+  // Hamiltonian
+  bool has_h = false;
+  std::vector<double> spe[2];
+  std::vector<trbl_tbme> tbme;
+  std::vector<MTerm> terms_pp, terms_nn, terms_pn;  // pn: a,c proton states; b,d neutron states
+  // J-coupled element -> m-scheme term contributions (for the gradient contraction)
+  std::vector<std::vector<std::pair<int, double>>> coef_pp, coef_nn, coef_pn;  // per term: (tbme idx, d h / d v)
+  int64_t work_items_per_nb[2] = {0, 0};
+  DeviceTables dt;
+  // sizes for kernels
+  int64_t np_total = 0, nn_total = 0;
+  int pj_count = 0, nj_count = 0;
+  int max_dn = 0, max_dp = 0;
+  std::vector<int> h_off_host, h_ncol_host;
+  std::vector<int64_t> blk_item0_host;  // prefix of rows per block (for row kernels)
+};
+
+// host helpers (model.cpp)
+void build_model(Model& m, const trbl_orbit* orbits, int n_orbits, int n_prot, int n_neut, int twoM, int parity);
+void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const trbl_tbme* v, int64_t n_v);
+double clebsch(int tj1, int tm1, int tj2, int tm2, int tJ, int tM);
+
+// device launchers (hv.hip)
+void launch_apply(const Model& m, int precision, int nb, const void* V, int64_t ldv, void* W, int64_t ldw,
+                  hipStream_t s);
+void launch_rank(const Model& m, const uint64_t* pb, const uint64_t* nb, int64_t n, int64_t* idx, hipStream_t s);
+void launch_unrank(const Model& m, const int64_t* idx, int64_t n, uint64_t* pb, uint64_t* nb, hipStream_t s);
+
+// solver (solver.cpp)
+int solve(const Model& m, const trbl_opts& o, double* evals, void* evecs, trbl_info* info);
+// gradient (grad.hip)
+void tbme_gradient(const Model& m, int n_eig, const double* w, const double* X, double* grad_v,
+                   double* grad_spe, hipStream_t s);
+
+}  // namespace trbl
+
+struct trbl_model {
+  trbl::Model m;
+};

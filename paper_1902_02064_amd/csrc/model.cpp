@@ -1,0 +1,519 @@
+// Host-side set-up of libtrbl: M-scheme basis (Sec. 2, App. A), J-coupled to
+// m-scheme conversion of the interaction (Sec. 2), and the tables the H.V
+// kernels read: identical-particle operator rows and one-body jumps (App. B).
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <tuple>
+
+#include "internal.h"
+
+namespace trbl {
+
+// ------------------------------------------------------------------ Clebsch-Gordan
+// Racah's closed formula in long double; arguments doubled. Factorials up to
+// 34! are needed for 2j <= 31; long double keeps ~19 digits.
+static long double lfact(int x2) {  // (x2/2)!
+  static std::vector<long double> tab;
+  if (tab.empty()) {
+    tab.resize(200);
+    tab[0] = 1.0L;
+    for (int i = 1; i < 200; i++) tab[i] = tab[i - 1] * (long double)i;
+  }
+  return tab[x2 / 2];
+}
+
+double clebsch(int tj1, int tm1, int tj2, int tm2, int tJ, int tM) {
+  if (tm1 + tm2 != tM) return 0.0;
+  if (tJ < std::abs(tj1 - tj2) || tJ > tj1 + tj2 || ((tj1 + tj2 + tJ) & 1)) return 0.0;
+  if (std::abs(tm1) > tj1 || std::abs(tm2) > tj2 || std::abs(tM) > tJ) return 0.0;
+  if (((tj1 + tm1) & 1) || ((tj2 + tm2) & 1) || ((tJ + tM) & 1)) return 0.0;
+  long double tri = lfact(tj1 + tj2 - tJ) * lfact(tj1 - tj2 + tJ) * lfact(-tj1 + tj2 + tJ) /
+                    lfact(tj1 + tj2 + tJ + 2);
+  long double pre = (long double)(tJ + 1) * tri * lfact(tj1 + tm1) * lfact(tj1 - tm1) * lfact(tj2 + tm2) *
+                    lfact(tj2 - tm2) * lfact(tJ + tM) * lfact(tJ - tM);
+  long double sum = 0.0L;
+  for (int k = 0; 2 * k <= tj1 + tj2 + 2; k++) {
+    int a[6] = {2 * k, tj1 + tj2 - tJ - 2 * k, tj1 - tm1 - 2 * k, tj2 + tm2 - 2 * k, tJ - tj2 + tm1 + 2 * k,
+                tJ - tj1 - tm2 + 2 * k};
+    bool ok = true;
+    for (int q = 0; q < 6; q++) ok = ok && a[q] >= 0;
+    if (!ok) continue;
+    long double den = 1.0L;
+    for (int q = 0; q < 6; q++) den *= lfact(a[q]);
+    sum += ((k & 1) ? -1.0L : 1.0L) / den;
+  }
+  return (double)(sqrtl(pre) * sum);
+}
+
+// ------------------------------------------------------------------ basis
+static int popc(uint64_t x) { return __builtin_popcountll(x); }
+
+// Jordan-Wigner sign of an operator on state s of one species: (-1)^(occupied below s).
+static int below_sign(uint64_t w, int s) {
+  uint64_t low = s ? (w & ((1ull << s) - 1)) : 0ull;
+  return (popc(low) & 1) ? -1 : 1;
+}
+
+static void enumerate_species(const Model& m, Species& S, int npart) {
+  S.npart = npart;
+  const int ns = m.ns;
+  const int norb = (int)m.orbits.size();
+  // count first to bound memory
+  long double total = 1.0L;
+  for (int i = 0; i < npart; i++) total = total * (ns - i) / (i + 1);
+  TRBL_REQUIRE(total < 4.0e8L, TRBL_E_INVALID, "species space too large to enumerate");
+  struct Item {
+    uint64_t part, rev, word;
+  };
+  std::map<std::pair<int, int>, std::vector<Item>> sec;  // (2M, -parity) -> items
+  auto visit = [&](uint64_t w) {
+    int tm = 0, lsum = 0;
+    int cnt[64] = {0};
+    uint64_t rev = 0;
+    for (uint64_t x = w; x; x &= x - 1) {
+      int s = __builtin_ctzll(x);
+      tm += m.st_tm[s];
+      lsum += m.orbits[m.st_orb[s]].l;
+      cnt[m.st_orb[s]]++;
+      rev |= 1ull << (ns - 1 - s);
+    }
+    uint64_t part = 0;
+    for (int o = 0; o < norb; o++) part = (part << 5) | (uint64_t)cnt[o];
+    int par = (lsum & 1) ? -1 : 1;
+    sec[{tm, -par}].push_back({part, rev, w});
+  };
+  if (npart == 0) {
+    visit(0);
+  } else {
+    uint64_t w = (npart == 64) ? ~0ull : ((1ull << npart) - 1);
+    const uint64_t limit = (ns == 64) ? 0ull : (1ull << ns);
+    while (true) {
+      visit(w);
+      // Gosper's hack: next larger word with the same popcount
+      uint64_t c = w & (~w + 1), r = w + c;
+      if (r == 0) break;
+      uint64_t nw = (((r ^ w) >> 2) / c) | r;
+      if (ns < 64 && nw >= limit) break;
+      if (nw <= w) break;
+      w = nw;
+    }
+  }
+  S.words.clear();
+  S.sectors.clear();
+  S.sector_of.clear();
+  S.part_key.clear();
+  S.index.clear();
+  for (auto& kv : sec) {
+    auto& v = kv.second;
+    std::sort(v.begin(), v.end(), [](const Item& a, const Item& b) {
+      if (a.part != b.part) return a.part > b.part;  // partitions: descending lexicographic
+      return a.rev > b.rev;                           // tuples: ascending lexicographic
+    });
+    SpeciesSector ss{kv.first.first, -kv.first.second, (int)S.words.size(), (int)v.size()};
+    int id = (int)S.sectors.size();
+    S.sectors.push_back(ss);
+    for (auto& it : v) {
+      S.index[it.word] = (int)S.words.size();
+      S.words.push_back(it.word);
+      S.part_key.push_back(it.part);
+      S.sector_of.push_back(id);
+    }
+  }
+}
+
+void build_model(Model& m, const trbl_orbit* orbits, int n_orbits, int n_prot, int n_neut, int twoM, int parity) {
+  TRBL_REQUIRE(orbits != nullptr && n_orbits > 0 && n_orbits <= 12, TRBL_E_INVALID, "need 1..12 orbits");
+  TRBL_REQUIRE(parity >= -1 && parity <= 1, TRBL_E_INVALID, "parity must be -1, 0 or +1");
+  m.orbits.assign(orbits, orbits + n_orbits);
+  m.ns = 0;
+  m.st_orb.clear();
+  m.st_tm.clear();
+  m.cl.tjmax = 0;
+  for (int o = 0; o < n_orbits; o++) {
+    const trbl_orbit& ob = orbits[o];
+    TRBL_REQUIRE(ob.twoj > 0 && (ob.twoj & 1) && ob.l >= 0 && ob.n >= 0, TRBL_E_INVALID, "bad orbit");
+    TRBL_REQUIRE(ob.twoj == 2 * ob.l + 1 || ob.twoj == 2 * ob.l - 1, TRBL_E_INVALID, "2j must be 2l +- 1");
+    for (int tm = -ob.twoj; tm <= ob.twoj; tm += 2) {
+      m.st_orb.push_back(o);
+      m.st_tm.push_back(tm);
+    }
+    m.cl.tjmax = std::max(m.cl.tjmax, ob.twoj);
+  }
+  m.ns = (int)m.st_orb.size();
+  TRBL_REQUIRE(m.ns <= 64, TRBL_E_TOO_MANY, "more than 64 m-states per species");
+  TRBL_REQUIRE(n_prot >= 0 && n_prot <= m.ns && n_neut >= 0 && n_neut <= m.ns, TRBL_E_INVALID,
+               "particle number out of range");
+  m.cl.nclass = (2 * m.cl.tjmax + 1) * 2;
+  m.n_prot = n_prot;
+  m.n_neut = n_neut;
+  m.twoM = twoM;
+  m.parity = parity;
+  enumerate_species(m, m.sp[0], n_prot);
+  enumerate_species(m, m.sp[1], n_neut);
+  // blocks: 2M_p ascending, proton parity + first, neutron parity + first
+  struct Key {
+    int tmp, pp, pn, kp, kn;
+  };
+  std::vector<Key> keys;
+  for (int kp = 0; kp < (int)m.sp[0].sectors.size(); kp++)
+    for (int kn = 0; kn < (int)m.sp[1].sectors.size(); kn++) {
+      const auto& a = m.sp[0].sectors[kp];
+      const auto& b = m.sp[1].sectors[kn];
+      if (a.twoM + b.twoM != twoM) continue;
+      if (parity != 0 && a.par * b.par != parity) continue;
+      keys.push_back({a.twoM, -a.par, -b.par, kp, kn});
+    }
+  std::sort(keys.begin(), keys.end(), [](const Key& x, const Key& y) {
+    return std::tie(x.tmp, x.pp, x.pn) < std::tie(y.tmp, y.pp, y.pn);
+  });
+  m.blocks.clear();
+  int64_t off = 0;
+  m.max_dn = m.max_dp = 0;
+  for (auto& k : keys) {
+    BlockInfo b;
+    b.psec = k.kp;
+    b.nsec = k.kn;
+    b.dp = m.sp[0].sectors[k.kp].size;
+    b.dn = m.sp[1].sectors[k.kn].size;
+    b.off = off;
+    off += (int64_t)b.dp * b.dn;
+    m.max_dn = std::max(m.max_dn, b.dn);
+    m.max_dp = std::max(m.max_dp, b.dp);
+    m.blocks.push_back(b);
+  }
+  m.dim = off;
+  TRBL_REQUIRE(m.dim > 0, TRBL_E_EMPTY, "empty M-scheme space");
+  m.np_total = (int64_t)m.sp[0].words.size();
+  m.nn_total = (int64_t)m.sp[1].words.size();
+
+  // device copies for rank / unrank and block layout
+  const int nb = (int)m.blocks.size();
+  std::vector<int> dp(nb), dn(nb), p0(nb), n0(nb);
+  std::vector<int64_t> boff(nb + 1);
+  for (int b = 0; b < nb; b++) {
+    dp[b] = m.blocks[b].dp;
+    dn[b] = m.blocks[b].dn;
+    p0[b] = m.sp[0].sectors[m.blocks[b].psec].start;
+    n0[b] = m.sp[1].sectors[m.blocks[b].nsec].start;
+    boff[b] = m.blocks[b].off;
+  }
+  boff[nb] = m.dim;
+  m.dt.blk_dp.upload(dp);
+  m.dt.blk_dn.upload(dn);
+  m.dt.blk_p0.upload(p0);
+  m.dt.blk_n0.upload(n0);
+  m.dt.blk_off.upload(boff);
+  // block of (proton sector, neutron sector) for device ranking
+  std::vector<int> bos(m.sp[0].sectors.size() * m.sp[1].sectors.size(), -1);
+  for (int b = 0; b < nb; b++) bos[m.blocks[b].psec * m.sp[1].sectors.size() + m.blocks[b].nsec] = b;
+  m.dt.blk_of_sec.upload(bos);
+  for (int s = 0; s < 2; s++) {
+    const Species& S = m.sp[s];
+    std::vector<int> st, sz, tm, pr;
+    for (auto& q : S.sectors) {
+      st.push_back(q.start);
+      sz.push_back(q.size);
+      tm.push_back(q.twoM);
+      pr.push_back(q.par);
+    }
+    (s == 0 ? m.dt.psec_tm : m.dt.nsec_tm).upload(tm);
+    (s == 0 ? m.dt.psec_par : m.dt.nsec_par).upload(pr);
+    (s == 0 ? m.dt.pwords : m.dt.nwords).upload(S.words);
+    (s == 0 ? m.dt.ppart : m.dt.npart).upload(S.part_key);
+    (s == 0 ? m.dt.psec_start : m.dt.nsec_start).upload(st);
+    (s == 0 ? m.dt.psec_size : m.dt.nsec_size).upload(sz);
+  }
+  // source block of each (target block, proton jump class)
+  const int ncl = m.cl.nclass;
+  std::vector<int> src(nb * ncl, -1);
+  std::map<std::tuple<int, int, int, int>, int> bidx;
+  for (int b = 0; b < nb; b++) {
+    const auto& a = m.sp[0].sectors[m.blocks[b].psec];
+    const auto& c = m.sp[1].sectors[m.blocks[b].nsec];
+    bidx[{a.twoM, a.par, c.twoM, c.par}] = b;
+  }
+  for (int b = 0; b < nb; b++) {
+    const auto& a = m.sp[0].sectors[m.blocks[b].psec];
+    const auto& c = m.sp[1].sectors[m.blocks[b].nsec];
+    for (int cls = 0; cls < ncl; cls++) {
+      int d2 = (cls / 2) * 2 - 2 * m.cl.tjmax;
+      int flip = cls % 2;
+      int fp = flip ? -1 : 1;
+      auto it = bidx.find({a.twoM + d2, a.par * fp, c.twoM - d2, c.par * fp});
+      if (it != bidx.end()) src[b * ncl + cls] = it->second;
+    }
+  }
+  m.dt.src_blk.upload(src);
+  m.has_h = false;
+}
+
+// ------------------------------------------------------------------ interaction
+namespace {
+
+struct TermKey {
+  int a, b, c, d;
+  bool operator<(const TermKey& o) const { return std::tie(a, b, c, d) < std::tie(o.a, o.b, o.c, o.d); }
+};
+
+struct TermAcc {
+  std::map<TermKey, int> id;
+  std::vector<MTerm> terms;
+  std::vector<std::vector<std::pair<int, double>>> coef;
+  void add(int a, int b, int c, int d, double dh_dv, double v, int t) {
+    auto it = id.find({a, b, c, d});
+    int k;
+    if (it == id.end()) {
+      k = (int)terms.size();
+      id[{a, b, c, d}] = k;
+      terms.push_back({a, b, c, d, 0.0});
+      coef.emplace_back();
+    } else {
+      k = it->second;
+    }
+    terms[k].h += dh_dv * v;
+    auto& cv = coef[k];
+    if (!cv.empty() && cv.back().first == t)
+      cv.back().second += dh_dv;
+    else
+      cv.push_back({t, dh_dv});
+  }
+};
+
+}  // namespace
+
+void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const trbl_tbme* v, int64_t n_v) {
+  TRBL_REQUIRE(spe_p && spe_n, TRBL_E_INVALID, "single-particle energies required");
+  TRBL_REQUIRE(n_v >= 0 && (n_v == 0 || v), TRBL_E_INVALID, "bad two-body list");
+  const int norb = (int)m.orbits.size();
+  const int ns = m.ns;
+  m.spe[0].assign(spe_p, spe_p + norb);
+  m.spe[1].assign(spe_n, spe_n + norb);
+  m.tbme.assign(v, v + n_v);
+  TermAcc acc[3];
+  auto twoj = [&](int o) { return m.orbits[o].twoj; };
+  for (int64_t t = 0; t < n_v; t++) {
+    trbl_tbme e = v[t];
+    TRBL_REQUIRE(e.channel >= 0 && e.channel <= 2, TRBL_E_INVALID, "channel must be 0, 1 or 2");
+    TRBL_REQUIRE(e.a >= 0 && e.a < norb && e.b >= 0 && e.b < norb && e.c >= 0 && e.c < norb && e.d >= 0 &&
+                     e.d < norb,
+                 TRBL_E_INVALID, "orbit index out of range");
+    TRBL_REQUIRE(e.twoJ >= 0 && !(e.twoJ & 1), TRBL_E_INVALID, "2J must be even and >= 0");
+    auto tri = [&](int x, int y) { return e.twoJ >= std::abs(twoj(x) - twoj(y)) && e.twoJ <= twoj(x) + twoj(y); };
+    TRBL_REQUIRE(tri(e.a, e.b) && tri(e.c, e.d), TRBL_E_INVALID, "J outside the triangle of a pair");
+    TRBL_REQUIRE(((m.orbits[e.a].l + m.orbits[e.b].l + m.orbits[e.c].l + m.orbits[e.d].l) & 1) == 0,
+                 TRBL_E_INVALID, "element breaks parity");
+    const bool ident = e.channel != 2;
+    if (ident) {
+      TRBL_REQUIRE(!(e.a == e.b && ((e.twoJ / 2) & 1)) && !(e.c == e.d && ((e.twoJ / 2) & 1)), TRBL_E_INVALID,
+                   "identical nucleons in one j-shell couple to even J only");
+      double val = e.v;
+      if (e.a > e.b) {
+        std::swap(e.a, e.b);
+        val *= -((((twoj(e.a) + twoj(e.b) - e.twoJ) / 2) & 1) ? -1.0 : 1.0);
+      }
+      if (e.c > e.d) {
+        std::swap(e.c, e.d);
+        val *= -((((twoj(e.c) + twoj(e.d) - e.twoJ) / 2) & 1) ? -1.0 : 1.0);
+      }
+      e.v = val;
+    }
+    // the pair of pair-states and its mirror
+    int prs[2][4] = {{e.a, e.b, e.c, e.d}, {e.c, e.d, e.a, e.b}};
+    int nmir = (e.a == e.c && e.b == e.d) ? 1 : 2;
+    for (int q = 0; q < nmir; q++) {
+      int A = prs[q][0], B = prs[q][1], C = prs[q][2], D = prs[q][3];
+      double nab = (ident && A == B) ? std::sqrt(2.0) : 1.0;
+      double ncd = (ident && C == D) ? std::sqrt(2.0) : 1.0;
+      for (int s1 = 0; s1 < ns; s1++) {
+        if (m.st_orb[s1] != A) continue;
+        for (int s2 = 0; s2 < ns; s2++) {
+          if (m.st_orb[s2] != B) continue;
+          if (ident && s2 <= s1) continue;
+          int tM = m.st_tm[s1] + m.st_tm[s2];
+          double c1 = clebsch(twoj(A), m.st_tm[s1], twoj(B), m.st_tm[s2], e.twoJ, tM);
+          if (c1 == 0.0) continue;
+          for (int s3 = 0; s3 < ns; s3++) {
+            if (m.st_orb[s3] != C) continue;
+            for (int s4 = 0; s4 < ns; s4++) {
+              if (m.st_orb[s4] != D) continue;
+              if (ident && s4 <= s3) continue;
+              if (m.st_tm[s3] + m.st_tm[s4] != tM) continue;
+              double c2 = clebsch(twoj(C), m.st_tm[s3], twoj(D), m.st_tm[s4], e.twoJ, tM);
+              if (c2 == 0.0) continue;
+              acc[e.channel].add(s1, s2, s3, s4, nab * ncd * c1 * c2, e.v, (int)t);
+            }
+          }
+        }
+      }
+    }
+  }
+  m.terms_pp = acc[0].terms;
+  m.terms_nn = acc[1].terms;
+  m.terms_pn = acc[2].terms;
+  m.coef_pp = acc[0].coef;
+  m.coef_nn = acc[1].coef;
+  m.coef_pn = acc[2].coef;
+
+  // ---------------- identical-particle operator rows (App. B, first part), per species
+  // Row g' of species s: <g'|H_ss|g> for every g reachable by a two-body jump, plus
+  // the single-particle energies on the diagonal. Terms are grouped by creation pair
+  // (a,b); the adjoint jump c+_c c+_d c_b c_a applied to g' gives g.
+  for (int s = 0; s < 2; s++) {
+    const Species& S = m.sp[s];
+    const std::vector<MTerm>& T = s == 0 ? m.terms_pp : m.terms_nn;
+    std::vector<std::vector<int>> by_pair(ns * ns);
+    for (int k = 0; k < (int)T.size(); k++) by_pair[T[k].a * ns + T[k].b].push_back(k);
+    const std::vector<double>& e1 = m.spe[s];
+    std::vector<int> ptr(1, 0), col;
+    std::vector<double> val;
+    std::vector<int> tptr(1, 0), tid;  // gradient: per entry, contributing (term, sign)
+    std::vector<int8_t> tsg;
+    std::vector<std::pair<int, std::pair<double, std::pair<int, int>>>> row;  // (g, (h, (term, sign)))
+    for (int g = 0; g < (int)S.words.size(); g++) {
+      uint64_t w = S.words[g];
+      row.clear();
+      double diag = 0.0;
+      for (uint64_t x = w; x; x &= x - 1) diag += e1[m.st_orb[__builtin_ctzll(x)]];
+      row.push_back({g, {diag, {-1, 0}}});
+      for (uint64_t x = w; x; x &= x - 1) {
+        int a = __builtin_ctzll(x);
+        for (uint64_t y = x & (x - 1); y; y &= y - 1) {
+          int b = __builtin_ctzll(y);
+          for (int k : by_pair[a * ns + b]) {
+            const MTerm& t = T[k];
+            uint64_t r = w;
+            int sg = below_sign(r, a);
+            r &= ~(1ull << a);
+            sg *= below_sign(r, b);
+            r &= ~(1ull << b);
+            if (r & (1ull << t.d)) continue;
+            sg *= below_sign(r, t.d);
+            r |= 1ull << t.d;
+            if (r & (1ull << t.c)) continue;
+            sg *= below_sign(r, t.c);
+            r |= 1ull << t.c;
+            auto it = S.index.find(r);
+            if (it == S.index.end()) continue;
+            row.push_back({it->second, {t.h * sg, {k, sg}}});
+          }
+        }
+      }
+      std::sort(row.begin(), row.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+      const int base = S.sectors[S.sector_of[g]].start;
+      for (size_t i = 0; i < row.size();) {
+        size_t j = i;
+        double h = 0.0;
+        while (j < row.size() && row[j].first == row[i].first) {
+          h += row[j].second.first;
+          if (row[j].second.second.first >= 0) {
+            tid.push_back(row[j].second.second.first);
+            tsg.push_back((int8_t)row[j].second.second.second);
+          }
+          j++;
+        }
+        col.push_back(row[i].first - base);
+        val.push_back(h);
+        tptr.push_back((int)tid.size());
+        i = j;
+      }
+      ptr.push_back((int)col.size());
+    }
+    std::vector<float> val32(val.begin(), val.end());
+    (s == 0 ? m.dt.pp_ptr : m.dt.nn_ptr).upload(ptr);
+    (s == 0 ? m.dt.pp_col : m.dt.nn_col).upload(col);
+    (s == 0 ? m.dt.pp_v64 : m.dt.nn_v64).upload(val);
+    (s == 0 ? m.dt.pp_v32 : m.dt.nn_v32).upload(val32);
+    (s == 0 ? m.dt.pp_tptr : m.dt.nn_tptr).upload(tptr);
+    (s == 0 ? m.dt.pp_tid : m.dt.nn_tid).upload(tid);
+    (s == 0 ? m.dt.pp_tsgn : m.dt.nn_tsgn).upload(tsg);
+  }
+
+  // ---------------- one-body jumps and the pn coefficient table (App. B, second part)
+  const Classes& cl = m.cl;
+  const int ncl = cl.nclass;
+  // op numbering inside each class, separately for the proton side (a,c) and neutron side (b,d)
+  std::vector<std::vector<std::pair<int, int>>> pops(ncl), nops(ncl);
+  std::vector<int> pop_idx(ns * ns), nop_idx(ns * ns), pop_cls(ns * ns), nop_cls(ns * ns);
+  for (int x = 0; x < ns; x++)
+    for (int y = 0; y < ns; y++) {
+      // proton op c+_x c_y: jump from target removes x, adds y; source 2M changes by tm[y]-tm[x]
+      int d2 = m.st_tm[y] - m.st_tm[x];
+      int flip = (m.orbits[m.st_orb[x]].l + m.orbits[m.st_orb[y]].l) & 1;
+      int c = cl.cls(d2, flip);
+      pop_cls[x * ns + y] = c;
+      pop_idx[x * ns + y] = (int)pops[c].size();
+      pops[c].push_back({x, y});
+      nop_cls[x * ns + y] = c;
+      nop_idx[x * ns + y] = (int)nops[c].size();
+      nops[c].push_back({x, y});
+    }
+  // table h[cls][op_p][op_n] over proton class cls and neutron class conj(cls)
+  std::vector<int> hoff(ncl + 1, 0), hncol(ncl, 0);
+  for (int c = 0; c < ncl; c++) {
+    hncol[c] = (int)nops[cl.conj(c)].size();
+    hoff[c + 1] = hoff[c] + (int)pops[c].size() * hncol[c];
+  }
+  std::vector<double> h(hoff[ncl], 0.0);
+  std::vector<int> hterm(hoff[ncl], -1);
+  for (int k = 0; k < (int)m.terms_pn.size(); k++) {
+    const MTerm& t = m.terms_pn[k];  // c+_a(p) c+_b(n) c_d(n) c_c(p): proton op (a,c), neutron op (b,d)
+    int c = pop_cls[t.a * ns + t.c];
+    int cn = nop_cls[t.b * ns + t.d];
+    TRBL_REQUIRE(cn == cl.conj(c), TRBL_E_INVALID, "pn term breaks M or parity conservation");
+    int at = hoff[c] + pop_idx[t.a * ns + t.c] * hncol[c] + nop_idx[t.b * ns + t.d];
+    h[at] += t.h;
+    hterm[at] = k;
+  }
+  m.h_off_host = hoff;
+  m.h_ncol_host = hncol;
+  std::vector<float> h32(h.begin(), h.end());
+  m.dt.h_off.upload(hoff);
+  m.dt.h_ncol.upload(hncol);
+  m.dt.h64.upload(h);
+  m.dt.h32.upload(h32);
+  m.dt.h_term.upload(hterm);
+  // jump lists: from each SD g' remove x in g', add y not in g' \ {x} (y == x allowed)
+  for (int s = 0; s < 2; s++) {
+    const Species& S = m.sp[s];
+    const std::vector<int>& oidx = s == 0 ? pop_idx : nop_idx;
+    const std::vector<int>& ocls = s == 0 ? pop_cls : nop_cls;
+    const int64_t nsd = (int64_t)S.words.size();
+    std::vector<int> start(nsd * ncl + 1, 0);
+    std::vector<int> jidx, jmeta;
+    std::vector<std::vector<std::pair<int, int>>> bucket(ncl);
+    for (int64_t g = 0; g < nsd; g++) {
+      for (auto& bk : bucket) bk.clear();
+      uint64_t w = S.words[g];
+      for (uint64_t xx = w; xx; xx &= xx - 1) {
+        int x = __builtin_ctzll(xx);
+        int sg = below_sign(w, x);
+        uint64_t r0 = w & ~(1ull << x);
+        for (int y = 0; y < ns; y++) {
+          if (r0 & (1ull << y)) continue;
+          int sy = sg * below_sign(r0, y);
+          uint64_t r = r0 | (1ull << y);
+          int gi = S.index.at(r);
+          int local = gi - S.sectors[S.sector_of[gi]].start;
+          int c = ocls[x * ns + y];
+          bucket[c].push_back({local, (oidx[x * ns + y] << 1) | (sy < 0 ? 1 : 0)});
+        }
+      }
+      for (int c = 0; c < ncl; c++) {
+        start[g * ncl + c] = (int)jidx.size();
+        for (auto& pr : bucket[c]) {
+          jidx.push_back(pr.first);
+          jmeta.push_back(pr.second);
+        }
+      }
+    }
+    start[nsd * ncl] = (int)jidx.size();
+    (s == 0 ? m.dt.pj_start : m.dt.nj_start).upload(start);
+    (s == 0 ? m.dt.pj_idx : m.dt.nj_idx).upload(jidx);
+    (s == 0 ? m.dt.pj_meta : m.dt.nj_meta).upload(jmeta);
+    (s == 0 ? m.pj_count : m.nj_count) = (int)jidx.size();
+  }
+  m.has_h = true;
+}
+
+}  // namespace trbl

@@ -1,0 +1,89 @@
+"""Parity of the HIP block H.V (trbl_apply) with the oracle's explicit H (GPU)."""
+import numpy as np
+import pytest
+
+from gpu_common import fp32_bound, fp64_bound, pair, say
+from workloads import PF_ORBITS, SD_ORBITS, SD_SPE, PF_SPE, WORKLOADS, random_block, random_tbme
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+MIXED_PAR = ((0, 1, 1), (0, 2, 5), (0, 1, 3))  # p1/2 d5/2 p3/2: both parities present
+
+CASES = [
+    # name, orbits, Z, N, 2M, parity, seed, nb
+    ("sd22_nb4", SD_ORBITS, 2, 2, 0, 0, 1, 4),
+    ("sd32_odd_nb3", SD_ORBITS, 3, 2, 1, 0, 2, 3),
+    ("sd22_m2_nb1", SD_ORBITS, 2, 2, 2, 0, 3, 1),
+    ("pf22_nb16", PF_ORBITS, 2, 2, 0, 0, 4, 16),
+    ("pf31_nb64", PF_ORBITS, 3, 1, 0, 0, 5, 64),
+    ("mixpar_pos_nb5", MIXED_PAR, 2, 2, 0, 1, 6, 5),
+    ("mixpar_neg_nb8", MIXED_PAR, 2, 1, 1, -1, 7, 8),
+    ("mixpar_both_nb2", MIXED_PAR, 1, 2, 1, 0, 8, 2),
+    ("sd_protons_only", SD_ORBITS, 3, 0, 1, 0, 9, 4),
+    ("sd_neutrons_only", SD_ORBITS, 0, 4, 0, 0, 10, 4),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: c[0])
+def test_apply_matches_dense_oracle(case):
+    name, orbits, z, n, twoM, par, seed, nb = case
+    say("case", name)
+    spe = [(-1.5 + 0.7 * k) for k in range(len(orbits))]
+    spn = [(0.3 - 0.4 * k) for k in range(len(orbits))]
+    g, o = pair(orbits, z, n, twoM, random_tbme(orbits, seed), spe, spn, par)
+    assert g.dim == o.dim
+    H = o.dense()
+    nnz = int(np.max(np.count_nonzero(H, axis=1)))
+    V = random_block(100 + seed, o.dim, nb)
+    ref = H @ V
+    bound = fp64_bound(np.abs(H) @ np.abs(V), nnz)
+    W = g.apply(torch.from_numpy(V).cuda()).cpu().numpy()
+    assert np.all(np.abs(W - ref) <= bound), np.max(np.abs(W - ref) / bound)
+    # mixed precision: FP32 vectors, FP32 coefficients, FP32 accumulation
+    V32 = V.astype(np.float32)
+    ref32 = H @ V32.astype(np.float64)
+    W32 = g.apply(torch.from_numpy(V32).cuda()).cpu().numpy().astype(np.float64)
+    b32 = fp32_bound(np.abs(H) @ np.abs(V32.astype(np.float64)), nnz)
+    assert np.all(np.abs(W32 - ref32) <= b32), np.max(np.abs(W32 - ref32) / b32)
+
+
+def test_apply_deterministic_and_linear():
+    g, o = pair(SD_ORBITS, 2, 2, 0, random_tbme(SD_ORBITS, 1), SD_SPE, SD_SPE, oracle=False)
+    V = torch.from_numpy(random_block(5, g.dim, 4)).cuda()
+    W1 = g.apply(V)
+    W2 = g.apply(V)
+    assert torch.equal(W1, W2)
+    # nb columns are independent: the single-column product equals the corresponding column
+    W3 = g.apply(V[:, 2:3].contiguous())
+    assert torch.equal(W3[:, 0], W1[:, 2])
+
+
+@pytest.mark.parametrize("wname,nrows", [("pf44", 300), ("sd66", 300)])
+def test_apply_full_size_sampled_rows(wname, nrows):
+    """Full-size workload in the bench's launch configuration; oracle rows computed one by one."""
+    w = WORKLOADS[wname]
+    say("case", wname, "full size")
+    g, o = pair(w.orbits, w.n_prot, w.n_neut, w.twoM, w.tbme(), w.spe, w.spe)
+    assert g.dim == o.dim
+    V = random_block(2000, g.dim, w.nb)
+    W = g.apply(torch.from_numpy(V).cuda()).cpu().numpy()
+    rng = np.random.default_rng(3)
+    idx = np.unique(np.concatenate([rng.choice(g.dim, nrows, replace=False), [0, g.dim - 1]]))
+    ref = o.apply_rows(V, idx)
+    ptr, col, val = o.rows(idx)
+    absHV = np.zeros_like(ref)
+    for r in range(len(idx)):
+        sl = slice(ptr[r], ptr[r + 1])
+        absHV[r] = np.abs(val[sl]) @ np.abs(V[col[sl]])
+    nnz = int(np.max(np.diff(ptr)))
+    assert np.all(np.abs(W[idx] - ref) <= fp64_bound(absHV, nnz))
+    # FP32 path on the same rows
+    V32 = V.astype(np.float32)
+    W32 = g.apply(torch.from_numpy(V32).cuda()).cpu().numpy().astype(np.float64)
+    ref32 = o.apply_rows(V32.astype(np.float64), idx)
+    absHV32 = np.zeros_like(ref)
+    for r in range(len(idx)):
+        sl = slice(ptr[r], ptr[r + 1])
+        absHV32[r] = np.abs(val[sl]) @ np.abs(V32[col[sl]].astype(np.float64))
+    assert np.all(np.abs(W32[idx] - ref32) <= fp32_bound(absHV32, nnz))
