@@ -1,0 +1,64 @@
+// Declarations of the dense block kernels (dense.hip) used by the TRBL driver.
+#pragma once
+#include <algorithm>
+
+#include "internal.h"
+
+namespace trbl {
+
+// Grow-only device scratch for per-workgroup partial sums.
+struct Scratch {
+  DevBuf buf;
+  int last_G = 0;
+  double* last_part = nullptr;
+  double* partials(size_t n) {
+    buf.alloc(n * sizeof(double));
+    return buf.as<double>();
+  }
+};
+
+// C (m x nb) = A^T B over D rows.
+template <class TA, class TB>
+void tn(const TA* A, int64_t lda, int m, const TB* B, int64_t ldb, int nb, int64_t D, double* C, Scratch& s,
+        hipStream_t st);
+// Bout = Bin - A C; mode 1 also forms A^T Bout into Pout, mode 2 keeps Bout^T Bout partials in s.
+template <class TA, class TI>
+void update(const TA* A, int64_t lda, int m, const double* C, const TI* Bin, int64_t ldi, double* Bout, int64_t ldo,
+            int nb, int64_t D, int mode, double* Pout, Scratch& s, hipStream_t st);
+// Bout = Bin R (R nb x nb); gram keeps Bout^T Bout partials in s.
+template <class TI, class TO>
+void apply_small(const TI* Bin, int64_t ldi, const double* R, TO* Bout, int64_t ldo, int nb, int64_t D, bool gram,
+                 Scratch& s, hipStream_t st);
+// Cholesky of the sum of G partial nb x nb Gram matrices: R, R^-1, beta = R Rprev (if beta), status.
+void chol(const double* part, int G, int nb, double* R, double* Rinv, const double* Rprev, double* beta, int* status,
+          hipStream_t st);
+// Y[:, 0:ncol] = A[:, 0:m] U (row-wise, in place allowed); then optional column block move.
+template <class TA, class TY>
+void rowgemm(const TA* A, int64_t lda, int m, const double* U, int64_t ldu, int ncol, TY* Y, int64_t ldy, int64_t D,
+             int vsrc, int vdst, int nv, hipStream_t st);
+template <class T>
+void random_block(T* out, int64_t ld, int64_t D, int nb, uint64_t seed, hipStream_t st);
+template <class TS, class TD>
+void copy_cols(const TS* src, int64_t lds_, TD* dst, int64_t ldd, int64_t D, int ncol, hipStream_t st);
+void t_alpha(double* T, int ldt, int c0, int nb, const double* C1, hipStream_t st);
+void t_beta(double* T, int ldt, int c0, int m, int nb, const double* beta, hipStream_t st);
+void resid(const double* beta, int nb, const double* U, int ldu, int m, int n, double* rho, hipStream_t st);
+void t_restart(double* T, int ldt, int lm, const double* theta, int ls, const double* beta, int nb, const double* U,
+               int ldu, int m, hipStream_t st);
+
+// Symmetric eigensolver of a small dense matrix (eig.hip): all eigenvalues ascending in theta[0:n],
+// orthonormal eigenvectors of the nvec lowest in U (n x nvec, ld ldu).
+struct EigWork {
+  DevBuf a, z, lu, aux;
+};
+void symeig(const double* T, int ldt, int n, int nvec, double* theta, double* U, int ldu, EigWork& w, bool orth,
+            hipStream_t st);
+// Generalised problem S y = theta G y (G positive definite, n x n): M = L^-1 S L^-T into M, L^-1 into Linv.
+void gen_reduce(const double* S, const double* G, int n, double* M, double* Linv, int* status, hipStream_t st);
+// Y = L^-T Yp (n x nv, ld ldy).
+void gen_back(const double* Linv, const double* Yp, int ldp, int n, int nv, double* Y, int ldy, hipStream_t st);
+// column norms of W - X diag(theta) over D rows: out[c] (squared sums accumulated, then sqrt on host side)
+void resid_cols(const double* W, int64_t ldw, const double* X, int64_t ldx, const double* theta, int ncol, int64_t D,
+                double* out, Scratch& s, hipStream_t st);
+
+}  // namespace trbl

@@ -1,0 +1,689 @@
+// Dense block kernels of TRBL (Alg. 4): projections V^T W, block Gram-Schmidt
+// updates W -= V C, Cholesky QR of the new block, and the restart combination
+// v_k := sum_j v_j U_jk (Sec. 3.4). All arithmetic is FP64; stored vectors may
+// be FP32 (mixed precision) and are widened on load.
+//
+// Matrix-core use: v_mfma_f64_16x16x4f64. Operand layout (one double per lane):
+//   A (16 x 4):  lane l holds A[l % 16][l / 16]
+//   B (4 x 16):  lane l holds B[l / 16][l % 16]
+//   D (16 x 16): lane l, register v holds D[l / 16 + 4 * v][l % 16], v = 0..3 (measured on gfx950)
+// In row-streaming products the k index of a 16-wide chunk is permuted so each
+// lane loads 4 consecutive values of one row (k = k0 + 4 * (l / 16) + t for
+// step t): the sum over k is unchanged and the loads are 128-byte coalesced.
+#include "dense.h"
+
+namespace trbl {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <class T>
+__device__ __forceinline__ double ld(const T* p) {
+  return (double)(*p);
+}
+
+// four consecutive values of a row, widened; masked beyond `valid`
+template <class T>
+__device__ __forceinline__ void ld4(const T* p, int valid, double out[4]) {
+  if (valid >= 4) {
+    if constexpr (sizeof(T) == 8) {
+      const double2* q = reinterpret_cast<const double2*>(p);
+      double2 x = q[0], y = q[1];
+      out[0] = x.x; out[1] = x.y; out[2] = y.x; out[3] = y.y;
+    } else {
+      float4 x = *reinterpret_cast<const float4*>(p);
+      out[0] = x.x; out[1] = x.y; out[2] = x.z; out[3] = x.w;
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < 4; t++) out[t] = (t < valid) ? (double)p[t] : 0.0;
+  }
+}
+
+// ------------------------------------------------------------------ C = A^T B (partial per workgroup)
+// A: [D][lda] (m columns used), B: [D][ldb] (nb columns). part[g] is m x nb row-major.
+template <class TA, class TB>
+__global__ __launch_bounds__(512) void tn_partial_kernel(const TA* __restrict__ A, int64_t lda, int m,
+                                                         const TB* __restrict__ B, int64_t ldb, int nb, int64_t D,
+                                                         int64_t rows_per, double* __restrict__ part) {
+  constexpr int WAVES = 8, MAXI = 6, MAXC = 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int mt = (m + 15) >> 4, ct = (nb + 15) >> 4;
+  d4 acc[MAXI][MAXC];
+#pragma unroll
+  for (int i = 0; i < MAXI; i++)
+#pragma unroll
+    for (int q = 0; q < MAXC; q++) acc[i][q] = d4{0, 0, 0, 0};
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per;
+  const int64_t r1 = min(D, r0 + rows_per);
+  const int li = lane & 15, lk = lane >> 4;
+  for (int64_t r = r0; r < r1; r += 4) {
+    const int64_t rr = r + lk;
+    const bool rok = rr < r1;
+    double bop[MAXC];
+#pragma unroll
+    for (int q = 0; q < MAXC; q++) {
+      const int c = q * 16 + li;
+      bop[q] = (q < ct && rok && c < nb) ? ld(B + rr * ldb + c) : 0.0;
+    }
+#pragma unroll
+    for (int ti = 0; ti < MAXI; ti++) {
+      const int it = wave + ti * WAVES;
+      if (it < mt) {
+        const int i = it * 16 + li;
+        const double aop = (rok && i < m) ? ld(A + rr * lda + i) : 0.0;
+#pragma unroll
+        for (int q = 0; q < MAXC; q++)
+          if (q < ct) acc[ti][q] = mfma(aop, bop[q], acc[ti][q]);
+      }
+    }
+  }
+  double* out = part + (int64_t)blockIdx.x * m * nb;
+#pragma unroll
+  for (int ti = 0; ti < MAXI; ti++) {
+    const int it = wave + ti * WAVES;
+    if (it >= mt) continue;
+#pragma unroll
+    for (int q = 0; q < MAXC; q++) {
+      if (q >= ct) continue;
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int i = it * 16 + lk + 4 * v, c = q * 16 + li;
+        if (i < m && c < nb) out[i * nb + c] = acc[ti][q][v];
+      }
+    }
+  }
+}
+
+__global__ void reduce_partials_kernel(const double* __restrict__ part, int G, int64_t len, double* __restrict__ out) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= len) return;
+  double s = 0.0;
+  for (int g = 0; g < G; g++) s += part[(int64_t)g * len + k];
+  out[k] = s;
+}
+
+// ------------------------------------------------------------------ Bout = Bin - A C (+ fused partial product)
+// mode 0: update only; mode 1: also part[g] += A^T Bout (m x nb); mode 2: also part[g] += Bout^T Bout (nb x nb).
+// C (m x nb, FP64) is staged in LDS, padded to 16-multiples with zeros.
+template <class TA, class TI, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void update_kernel(const TA* __restrict__ A, int64_t lda, int m,
+                                                     const double* __restrict__ C, const TI* Bin, int64_t ldi,
+                                                     double* Bout, int64_t ldo, int nb, int64_t D, int mode,
+                                                     double* __restrict__ part) {
+  constexpr int ROWS = WAVES * 16, MAXI = 48 / WAVES, MAXC = 4;
+  extern __shared__ double lds[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int mt = (m + 15) >> 4, ct = (nb + 15) >> 4;
+  const int mp = mt * 16, nbp = ct * 16;
+  double* Cs = lds;                 // mp x nbp
+  double* Wt = lds + mp * nbp;      // ROWS x nbp
+  for (int e = threadIdx.x; e < mp * nbp; e += blockDim.x) {
+    const int k = e / nbp, c = e % nbp;
+    Cs[e] = (k < m && c < nb) ? C[k * nb + c] : 0.0;
+  }
+  __syncthreads();
+  const int li = lane & 15, lk = lane >> 4;
+  d4 pacc[MAXI][MAXC];
+#pragma unroll
+  for (int i = 0; i < MAXI; i++)
+#pragma unroll
+    for (int q = 0; q < MAXC; q++) pacc[i][q] = d4{0, 0, 0, 0};
+  const int64_t ntiles = (D + ROWS - 1) / ROWS;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t rbase = tile * ROWS;
+    // ---- phase 1: each wave updates its 16 rows
+    const int64_t rw = rbase + wave * 16;
+    d4 acc[MAXC];
+#pragma unroll
+    for (int q = 0; q < MAXC; q++) acc[q] = d4{0, 0, 0, 0};
+    const int64_t ra = rw + li;  // row this lane loads for the A operand
+    for (int k0 = 0; k0 < m; k0 += 16) {
+      const int kk = k0 + 4 * lk;
+      double a4[4];
+      if (ra < D) ld4(A + ra * lda + kk, m - kk, a4);
+      else a4[0] = a4[1] = a4[2] = a4[3] = 0.0;
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+#pragma unroll
+        for (int q = 0; q < MAXC; q++)
+          if (q < ct) acc[q] = mfma(a4[t], Cs[(kk + t) * nbp + q * 16 + li], acc[q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < MAXC; q++) {
+      if (q >= ct) continue;
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int rl = wave * 16 + lk + 4 * v;
+        const int64_t r = rbase + rl;
+        const int c = q * 16 + li;
+        double val = 0.0;
+        if (r < D && c < nb) {
+          val = ld(Bin + r * ldi + c) - acc[q][v];
+          Bout[r * ldo + c] = val;
+        }
+        Wt[rl * nbp + c] = val;
+      }
+    }
+    if (mode == 0) continue;
+    __syncthreads();
+    // ---- phase 2: fused partial product over the ROWS rows of this tile
+    if (mode == 1) {
+      for (int s = 0; s < ROWS / 4; s++) {
+        const int rl = 4 * s + lk;
+        const int64_t r = rbase + rl;
+        double bop[MAXC];
+#pragma unroll
+        for (int q = 0; q < MAXC; q++) bop[q] = (q < ct) ? Wt[rl * nbp + q * 16 + li] : 0.0;
+#pragma unroll
+        for (int ti = 0; ti < MAXI; ti++) {
+          const int it = wave + ti * WAVES;
+          if (it < mt) {
+            const int i = it * 16 + li;
+            const double aop = (r < D && i < m) ? ld(A + r * lda + i) : 0.0;
+#pragma unroll
+            for (int q = 0; q < MAXC; q++)
+              if (q < ct) pacc[ti][q] = mfma(aop, bop[q], pacc[ti][q]);
+          }
+        }
+      }
+    } else {
+      // Gram of the tile: wave w takes row quads w, w+WAVES, ...; tiles (qi, qj) in pacc[qi][qj]
+      for (int s = wave; s < ROWS / 4; s += WAVES) {
+        const int rl = 4 * s + lk;
+#pragma unroll
+        for (int qi = 0; qi < MAXC; qi++) {
+          if (qi >= ct) continue;
+          const double aop = Wt[rl * nbp + qi * 16 + li];
+#pragma unroll
+          for (int qj = 0; qj < MAXC; qj++)
+            if (qj < ct) pacc[qi][qj] = mfma(aop, Wt[rl * nbp + qj * 16 + li], pacc[qi][qj]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (mode == 0) return;
+  double* out = part + (int64_t)blockIdx.x * (mode == 1 ? (int64_t)m * nb : (int64_t)nb * nb);
+  if (mode == 1) {
+#pragma unroll
+    for (int ti = 0; ti < MAXI; ti++) {
+      const int it = wave + ti * WAVES;
+      if (it >= mt) continue;
+#pragma unroll
+      for (int q = 0; q < MAXC; q++) {
+        if (q >= ct) continue;
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+          const int i = it * 16 + lk + 4 * v, c = q * 16 + li;
+          if (i < m && c < nb) out[i * nb + c] = pacc[ti][q][v];
+        }
+      }
+    }
+  } else {
+    // reduce the per-wave Gram tiles through LDS, one wave after the other
+    double* red = lds;  // nbp x nbp; all phases are done
+    __syncthreads();
+    for (int e = threadIdx.x; e < nbp * nbp; e += blockDim.x) red[e] = 0.0;
+    for (int w = 0; w < WAVES; w++) {
+      __syncthreads();
+      if (wave != w) continue;
+#pragma unroll
+      for (int qi = 0; qi < MAXC; qi++) {
+        if (qi >= ct) continue;
+#pragma unroll
+        for (int qj = 0; qj < MAXC; qj++) {
+          if (qj >= ct) continue;
+#pragma unroll
+          for (int v = 0; v < 4; v++) red[(qi * 16 + lk + 4 * v) * nbp + qj * 16 + li] += pacc[qi][qj][v];
+        }
+      }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+      const int i = e / nb, c = e % nb;
+      const double s = red[i * nbp + c];
+      out[e] = s;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ Bout = Bin R  (R: nb x nb), optional Gram partial
+template <class TI, class TO>
+__global__ __launch_bounds__(256) void apply_small_kernel(const TI* Bin, int64_t ldi, const double* __restrict__ R,
+                                                          TO* Bout, int64_t ldo, int nb, int64_t D, int gram,
+                                                          double* __restrict__ part) {
+  extern __shared__ double lds[];
+  double* Rs = lds;                 // nb x nb
+  const int rows = max(1, 256 / nb);
+  double* tile = lds + nb * nb;     // rows x nb inputs
+  double* outt = tile + rows * nb;  // rows x nb outputs
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) Rs[e] = R[e];
+  const int npair = nb * nb;
+  double g[16];
+  const int gper = (npair + blockDim.x - 1) / blockDim.x;
+  for (int q = 0; q < 16; q++) g[q] = 0.0;
+  __syncthreads();
+  const int64_t ntiles = (D + rows - 1) / rows;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t r0 = t * rows;
+    for (int e = threadIdx.x; e < rows * nb; e += blockDim.x) {
+      const int64_t r = r0 + e / nb;
+      tile[e] = (r < D) ? ld(Bin + r * ldi + e % nb) : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < rows * nb; e += blockDim.x) {
+      const int rl = e / nb, c = e % nb;
+      double s = 0.0;
+      for (int k = 0; k < nb; k++) s += tile[rl * nb + k] * Rs[k * nb + c];
+      outt[e] = s;
+      const int64_t r = r0 + rl;
+      if (r < D) Bout[r * ldo + c] = (TO)s;
+    }
+    __syncthreads();
+    if (gram) {
+      for (int q = 0; q < gper && q < 16; q++) {
+        const int pidx = threadIdx.x + q * blockDim.x;
+        if (pidx < npair) {
+          const int i = pidx / nb, j = pidx % nb;
+          double s = 0.0;
+          for (int rl = 0; rl < rows; rl++) s += outt[rl * nb + i] * outt[rl * nb + j];
+          g[q] += s;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (gram) {
+    double* out = part + (int64_t)blockIdx.x * npair;
+    for (int q = 0; q < gper && q < 16; q++) {
+      const int pidx = threadIdx.x + q * blockDim.x;
+      if (pidx < npair) out[pidx] = g[q];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ Cholesky of the nb x nb Gram matrix
+// Sums G partials, factors G = R^T R (R upper, positive diagonal), inverts R,
+// and optionally forms beta = R * Rprev. status[0] = 0 ok, 1 not positive definite.
+__global__ __launch_bounds__(256) void chol_kernel(const double* __restrict__ part, int G, int nb, double* R,
+                                                   double* Rinv, const double* Rprev, double* beta, int* status) {
+  extern __shared__ double lds[];
+  double* A = lds;            // nb x nb
+  double* Ri = lds + nb * nb; // nb x nb
+  const int n2 = nb * nb;
+  for (int e = threadIdx.x; e < n2; e += blockDim.x) {
+    double s = 0.0;
+    for (int g = 0; g < G; g++) s += part[(int64_t)g * n2 + e];
+    A[e] = s;
+  }
+  __syncthreads();
+  __shared__ int bad;
+  __shared__ double dmax;
+  if (threadIdx.x == 0) {
+    bad = 0;
+    double mx = 0.0;
+    for (int i = 0; i < nb; i++) mx = fmax(mx, fabs(A[i * nb + i]));
+    dmax = mx;
+  }
+  __syncthreads();
+  // right-looking Cholesky on the upper triangle
+  for (int k = 0; k < nb; k++) {
+    if (threadIdx.x == 0) {
+      const double piv = A[k * nb + k];
+      if (!(piv > 1e-28 * dmax) || !(dmax > 0.0)) bad = 1;
+      A[k * nb + k] = sqrt(fmax(piv, 1e-300));
+    }
+    __syncthreads();
+    const double rkk = A[k * nb + k];
+    for (int j = k + 1 + threadIdx.x; j < nb; j += blockDim.x) A[k * nb + j] /= rkk;
+    __syncthreads();
+    for (int e = threadIdx.x; e < n2; e += blockDim.x) {
+      const int i = e / nb, j = e % nb;
+      if (i > k && j >= i) A[i * nb + j] -= A[k * nb + i] * A[k * nb + j];
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < n2; e += blockDim.x) {
+    const int i = e / nb, j = e % nb;
+    if (j < i) A[e] = 0.0;
+  }
+  __syncthreads();
+  // inverse of the upper-triangular R, column by column (one thread per column)
+  for (int j = threadIdx.x; j < nb; j += blockDim.x) {
+    for (int i = 0; i < nb; i++) Ri[i * nb + j] = 0.0;
+    Ri[j * nb + j] = 1.0 / A[j * nb + j];
+    for (int i = j - 1; i >= 0; i--) {
+      double s = 0.0;
+      for (int k = i + 1; k <= j; k++) s += A[i * nb + k] * Ri[k * nb + j];
+      Ri[i * nb + j] = -s / A[i * nb + i];
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n2; e += blockDim.x) {
+    R[e] = A[e];
+    Rinv[e] = Ri[e];
+    if (beta) {
+      const int i = e / nb, j = e % nb;
+      double s = 0.0;
+      for (int k = 0; k < nb; k++) s += A[i * nb + k] * Rprev[k * nb + j];
+      beta[e] = s;
+    }
+  }
+  if (threadIdx.x == 0) status[0] = bad;
+}
+
+// ------------------------------------------------------------------ Y = A U (row-wise), optionally in place
+// Y[r, 0:ncol] = A[r, 0:m] U[0:m, 0:ncol] (U row-major, ld ldu). In place (Y == A) is allowed:
+// every workgroup reads all of its rows before it writes them. If vsrc >= 0, columns
+// [vsrc, vsrc+nv) of A are copied to columns [vdst, vdst+nv) of Y after the product.
+template <class TA, class TY, int NT>
+__global__ __launch_bounds__(512) void rowgemm_kernel(const TA* A, int64_t lda, int m, const double* __restrict__ U,
+                                                      int64_t ldu, int ncol, TY* Y, int64_t ldy, int64_t D, int vsrc,
+                                                      int vdst, int nv) {
+  constexpr int WAVES = 8, ROWS = WAVES * 16, KC = 16;
+  extern __shared__ double lds[];
+  double* Us = lds;                      // KC x (NT*16)
+  double* Vs = lds + KC * NT * 16;       // ROWS x nv (copy of the moved block)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int ctile = (ncol + 15) >> 4;
+  const int64_t ntiles = (D + ROWS - 1) / ROWS;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t rbase = tile * ROWS;
+    if (vsrc >= 0) {
+      for (int e = threadIdx.x; e < ROWS * nv; e += blockDim.x) {
+        const int64_t r = rbase + e / nv;
+        Vs[e] = (r < D) ? ld(A + r * lda + vsrc + e % nv) : 0.0;
+      }
+    }
+    d4 acc[NT];
+#pragma unroll
+    for (int q = 0; q < NT; q++) acc[q] = d4{0, 0, 0, 0};
+    const int64_t ra = rbase + wave * 16 + li;
+    for (int k0 = 0; k0 < m; k0 += KC) {
+      __syncthreads();
+      for (int e = threadIdx.x; e < KC * NT * 16; e += blockDim.x) {
+        const int k = k0 + e / (NT * 16), c = e % (NT * 16);
+        Us[e] = (k < m && c < ncol) ? U[k * ldu + c] : 0.0;
+      }
+      __syncthreads();
+      const int kk = 4 * lk;
+      double a4[4];
+      if (ra < D) ld4(A + ra * lda + k0 + kk, m - (k0 + kk), a4);
+      else a4[0] = a4[1] = a4[2] = a4[3] = 0.0;
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+#pragma unroll
+        for (int q = 0; q < NT; q++)
+          if (q < ctile) acc[q] = mfma(a4[t], Us[(kk + t) * NT * 16 + q * 16 + li], acc[q]);
+      }
+    }
+    __syncthreads();  // all waves of the tile have finished reading A before anyone writes Y
+#pragma unroll
+    for (int q = 0; q < NT; q++) {
+      if (q >= ctile) continue;
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int64_t r = rbase + wave * 16 + lk + 4 * v;
+        const int c = q * 16 + li;
+        if (r < D && c < ncol) Y[r * ldy + c] = (TY)acc[q][v];
+      }
+    }
+    if (vsrc >= 0) {
+      for (int e = threadIdx.x; e < ROWS * nv; e += blockDim.x) {
+        const int64_t r = rbase + e / nv;
+        if (r < D) Y[r * ldy + vdst + e % nv] = (TY)Vs[e];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ small helpers
+// Standard normals: element (i, c) is normal number i*nb + c of splitmix64(seed) + Box-Muller.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t counter) {
+  uint64_t z = seed + (counter + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+template <class T>
+__global__ void random_kernel(T* out, int64_t ld, int64_t D, int nb, uint64_t seed) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= D * nb) return;
+  const uint64_t k = (uint64_t)e;
+  const double u1 = ((double)(splitmix64(seed, 2 * k) >> 11) + 1.0) * (1.0 / 9007199254740992.0);
+  const double u2 = ((double)(splitmix64(seed, 2 * k + 1) >> 11) + 1.0) * (1.0 / 9007199254740992.0);
+  const double z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+  out[(e / nb) * ld + e % nb] = (T)z;
+}
+
+template <class TS, class TD>
+__global__ void copy_cols_kernel(const TS* src, int64_t lds_, TD* dst, int64_t ldd, int64_t D, int ncol) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= D * ncol) return;
+  const int64_t r = e / ncol;
+  const int c = (int)(e % ncol);
+  dst[r * ldd + c] = (TD)src[r * lds_ + c];
+}
+
+// T-matrix bookkeeping of Alg. 4 (device-resident T, leading dimension ldt)
+__global__ void t_alpha_kernel(double* T, int ldt, int c0, int nb, const double* C1) {
+  // alpha_k = V_k^T W is rows c0..c0+nb of C1 (m x nb); symmetrised
+  const int e = threadIdx.x + blockIdx.x * blockDim.x;
+  if (e >= nb * nb) return;
+  const int i = e / nb, j = e % nb;
+  T[(c0 + i) * ldt + c0 + j] = 0.5 * (C1[(c0 + i) * nb + j] + C1[(c0 + j) * nb + i]);
+}
+
+__global__ void t_beta_kernel(double* T, int ldt, int c0, int m, int nb, const double* beta) {
+  const int e = threadIdx.x + blockIdx.x * blockDim.x;
+  if (e >= nb * nb) return;
+  const int i = e / nb, j = e % nb;
+  T[(m + i) * ldt + c0 + j] = beta[i * nb + j];
+  T[(c0 + j) * ldt + m + i] = beta[i * nb + j];
+}
+
+// residual norms rho_i = || beta U[m-nb:m, i] || for i < n
+__global__ void resid_kernel(const double* beta, int nb, const double* U, int ldu, int m, int n, double* rho) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int a = 0; a < nb; a++) {
+    double x = 0.0;
+    for (int b = 0; b < nb; b++) x += beta[a * nb + b] * U[(m - nb + b) * ldu + i];
+    s += x * x;
+  }
+  rho[i] = sqrt(s);
+}
+
+// restart: T := [diag(theta_1..ls)  r^T ; r  .], r = beta U[m-nb:m, 0:ls] (T zeroed first)
+__global__ void t_restart_fill_kernel(double* T, int ldt, const double* theta, int ls, const double* beta, int nb,
+                                      const double* U, int ldu, int m) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < ls) T[e * ldt + e] = theta[e];
+  if (e < nb * ls) {
+    const int a = e / ls, k = e % ls;
+    double s = 0.0;
+    for (int b = 0; b < nb; b++) s += beta[a * nb + b] * U[(m - nb + b) * ldu + k];
+    T[(ls + a) * ldt + k] = s;
+    T[k * ldt + ls + a] = s;
+  }
+}
+
+// ------------------------------------------------------------------ host launchers
+static int grid_for(int64_t rows, int64_t rows_per_wg, int cap) {
+  int64_t g = (rows + rows_per_wg - 1) / rows_per_wg;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
+
+template <class TA, class TB>
+void tn(const TA* A, int64_t lda, int m, const TB* B, int64_t ldb, int nb, int64_t D, double* C, Scratch& s,
+        hipStream_t st) {
+  TRBL_REQUIRE(m <= 8 * 6 * 16 && nb <= 64, TRBL_E_INVALID, "projection too wide");
+  int G = grid_for(D, 256, 1024);
+  int64_t rows_per = ((D + G - 1) / G + 3) / 4 * 4;
+  G = (int)((D + rows_per - 1) / rows_per);
+  double* part = s.partials((size_t)G * m * nb);
+  hipLaunchKernelGGL((tn_partial_kernel<TA, TB>), dim3(G), dim3(512), 0, st, A, lda, m, B, ldb, nb, D, rows_per, part);
+  const int64_t len = (int64_t)m * nb;
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, part, G, len, C);
+  TRBL_HIP(hipGetLastError());
+}
+
+template <class TA, class TI>
+void update(const TA* A, int64_t lda, int m, const double* C, const TI* Bin, int64_t ldi, double* Bout, int64_t ldo,
+            int nb, int64_t D, int mode, double* Pout, Scratch& s, hipStream_t st) {
+  TRBL_REQUIRE(m <= 768 && nb <= 64, TRBL_E_INVALID, "projection too wide");
+  const int mt = (m + 15) / 16, ct = (nb + 15) / 16;
+  auto shm_for = [&](int waves) {
+    size_t b = (size_t)(mt * 16 * ct * 16 + waves * 16 * ct * 16) * sizeof(double);
+    return std::max(b, (size_t)ct * 16 * ct * 16 * sizeof(double));
+  };
+  const int waves = (shm_for(8) <= 160 * 1024 && mt <= 48) ? 8 : 4;
+  const size_t shm = shm_for(waves);
+  TRBL_REQUIRE(shm <= 160 * 1024 && (mt + waves - 1) / waves <= 48 / waves, TRBL_E_INVALID,
+               "update tile does not fit in LDS");
+  int G = grid_for(D, waves * 16 * 4, 1024);
+  const int64_t plen = mode == 1 ? (int64_t)m * nb : (int64_t)nb * nb;
+  double* part = mode ? s.partials((size_t)G * plen) : nullptr;
+  if (waves == 8)
+    hipLaunchKernelGGL((update_kernel<TA, TI, 8>), dim3(G), dim3(512), shm, st, A, lda, m, C, Bin, ldi, Bout, ldo,
+                       nb, D, mode, part);
+  else
+    hipLaunchKernelGGL((update_kernel<TA, TI, 4>), dim3(G), dim3(256), shm, st, A, lda, m, C, Bin, ldi, Bout, ldo,
+                       nb, D, mode, part);
+  if (mode) {
+    if (Pout)
+      hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((plen + 255) / 256)), dim3(256), 0, st, part, G,
+                         plen, Pout);
+    s.last_G = G;
+    s.last_part = part;
+  }
+  TRBL_HIP(hipGetLastError());
+}
+
+template <class TI, class TO>
+void apply_small(const TI* Bin, int64_t ldi, const double* R, TO* Bout, int64_t ldo, int nb, int64_t D, bool gram,
+                 Scratch& s, hipStream_t st) {
+  const int rows = std::max(1, 256 / nb);
+  const int G = grid_for(D, rows * 8, 1024);
+  double* part = gram ? s.partials((size_t)G * nb * nb) : nullptr;
+  const size_t shm = (size_t)(nb * nb + 2 * rows * nb) * sizeof(double);
+  hipLaunchKernelGGL((apply_small_kernel<TI, TO>), dim3(G), dim3(256), shm, st, Bin, ldi, R, Bout, ldo, nb, D,
+                     gram ? 1 : 0, part);
+  if (gram) {
+    s.last_G = G;
+    s.last_part = part;
+  }
+  TRBL_HIP(hipGetLastError());
+}
+
+void chol(const double* part, int G, int nb, double* R, double* Rinv, const double* Rprev, double* beta, int* status,
+          hipStream_t st) {
+  const size_t shm = 2 * (size_t)nb * nb * sizeof(double);
+  hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(256), shm, st, part, G, nb, R, Rinv, Rprev, beta, status);
+  TRBL_HIP(hipGetLastError());
+}
+
+template <class TA, class TY>
+void rowgemm(const TA* A, int64_t lda, int m, const double* U, int64_t ldu, int ncol, TY* Y, int64_t ldy, int64_t D,
+             int vsrc, int vdst, int nv, hipStream_t st) {
+  const int G = grid_for(D, 128, 2048);
+  const int nt = (ncol + 15) / 16;
+  auto shm = [&](int NT) { return (size_t)(16 * NT * 16 + 128 * std::max(nv, 1)) * sizeof(double); };
+  if (nt <= 4)
+    hipLaunchKernelGGL((rowgemm_kernel<TA, TY, 4>), dim3(G), dim3(512), shm(4), st, A, lda, m, U, ldu, ncol, Y, ldy,
+                       D, vsrc, vdst, nv);
+  else if (nt <= 8)
+    hipLaunchKernelGGL((rowgemm_kernel<TA, TY, 8>), dim3(G), dim3(512), shm(8), st, A, lda, m, U, ldu, ncol, Y, ldy,
+                       D, vsrc, vdst, nv);
+  else if (nt <= 13)
+    hipLaunchKernelGGL((rowgemm_kernel<TA, TY, 13>), dim3(G), dim3(512), shm(13), st, A, lda, m, U, ldu, ncol, Y,
+                       ldy, D, vsrc, vdst, nv);
+  else {
+    // wide outputs: column groups of 13 tiles; only valid out of place
+    TRBL_REQUIRE((const void*)A != (const void*)Y || vsrc < 0, TRBL_E_INVALID, "in-place rowgemm too wide");
+    for (int c0 = 0; c0 < ncol; c0 += 13 * 16) {
+      const int nc = std::min(13 * 16, ncol - c0);
+      hipLaunchKernelGGL((rowgemm_kernel<TA, TY, 13>), dim3(G), dim3(512), shm(13), st, A, lda, m, U + c0, ldu, nc,
+                         Y + c0, ldy, D, -1, 0, 0);
+    }
+  }
+  TRBL_HIP(hipGetLastError());
+}
+
+template <class T>
+void random_block(T* out, int64_t ld, int64_t D, int nb, uint64_t seed, hipStream_t st) {
+  const int64_t n = D * nb;
+  hipLaunchKernelGGL(random_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, out, ld, D, nb, seed);
+  TRBL_HIP(hipGetLastError());
+}
+
+template <class TS, class TD>
+void copy_cols(const TS* src, int64_t lds_, TD* dst, int64_t ldd, int64_t D, int ncol, hipStream_t st) {
+  const int64_t n = D * ncol;
+  hipLaunchKernelGGL((copy_cols_kernel<TS, TD>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, lds_, dst,
+                     ldd, D, ncol);
+  TRBL_HIP(hipGetLastError());
+}
+
+void t_alpha(double* T, int ldt, int c0, int nb, const double* C1, hipStream_t st) {
+  hipLaunchKernelGGL(t_alpha_kernel, dim3((nb * nb + 255) / 256), dim3(256), 0, st, T, ldt, c0, nb, C1);
+}
+void t_beta(double* T, int ldt, int c0, int m, int nb, const double* beta, hipStream_t st) {
+  hipLaunchKernelGGL(t_beta_kernel, dim3((nb * nb + 255) / 256), dim3(256), 0, st, T, ldt, c0, m, nb, beta);
+}
+void resid(const double* beta, int nb, const double* U, int ldu, int m, int n, double* rho, hipStream_t st) {
+  hipLaunchKernelGGL(resid_kernel, dim3((n + 255) / 256), dim3(256), 0, st, beta, nb, U, ldu, m, n, rho);
+}
+void t_restart(double* T, int ldt, int lm, const double* theta, int ls, const double* beta, int nb, const double* U,
+               int ldu, int m, hipStream_t st) {
+  TRBL_HIP(hipMemsetAsync(T, 0, sizeof(double) * (size_t)lm * ldt, st));
+  const int n = std::max(ls, nb * ls);
+  hipLaunchKernelGGL(t_restart_fill_kernel, dim3((n + 255) / 256), dim3(256), 0, st, T, ldt, theta, ls, beta, nb, U,
+                     ldu, m);
+  TRBL_HIP(hipGetLastError());
+}
+
+// explicit instantiations
+template void tn<double, double>(const double*, int64_t, int, const double*, int64_t, int, int64_t, double*, Scratch&,
+                                 hipStream_t);
+template void tn<float, float>(const float*, int64_t, int, const float*, int64_t, int, int64_t, double*, Scratch&,
+                               hipStream_t);
+template void tn<float, double>(const float*, int64_t, int, const double*, int64_t, int, int64_t, double*, Scratch&,
+                                hipStream_t);
+template void tn<double, float>(const double*, int64_t, int, const float*, int64_t, int, int64_t, double*, Scratch&,
+                                hipStream_t);
+template void update<double, double>(const double*, int64_t, int, const double*, const double*, int64_t, double*,
+                                     int64_t, int, int64_t, int, double*, Scratch&, hipStream_t);
+template void update<float, float>(const float*, int64_t, int, const double*, const float*, int64_t, double*, int64_t,
+                                   int, int64_t, int, double*, Scratch&, hipStream_t);
+template void update<float, double>(const float*, int64_t, int, const double*, const double*, int64_t, double*,
+                                    int64_t, int, int64_t, int, double*, Scratch&, hipStream_t);
+template void apply_small<double, double>(const double*, int64_t, const double*, double*, int64_t, int, int64_t, bool,
+                                          Scratch&, hipStream_t);
+template void apply_small<double, float>(const double*, int64_t, const double*, float*, int64_t, int, int64_t, bool,
+                                         Scratch&, hipStream_t);
+template void apply_small<float, double>(const float*, int64_t, const double*, double*, int64_t, int, int64_t, bool,
+                                         Scratch&, hipStream_t);
+template void rowgemm<double, double>(const double*, int64_t, int, const double*, int64_t, int, double*, int64_t,
+                                      int64_t, int, int, int, hipStream_t);
+template void rowgemm<float, float>(const float*, int64_t, int, const double*, int64_t, int, float*, int64_t, int64_t,
+                                    int, int, int, hipStream_t);
+template void rowgemm<float, double>(const float*, int64_t, int, const double*, int64_t, int, double*, int64_t,
+                                     int64_t, int, int, int, hipStream_t);
+template void random_block<double>(double*, int64_t, int64_t, int, uint64_t, hipStream_t);
+template void random_block<float>(float*, int64_t, int64_t, int, uint64_t, hipStream_t);
+template void copy_cols<double, double>(const double*, int64_t, double*, int64_t, int64_t, int, hipStream_t);
+template void copy_cols<float, float>(const float*, int64_t, float*, int64_t, int64_t, int, hipStream_t);
+template void copy_cols<float, double>(const float*, int64_t, double*, int64_t, int64_t, int, hipStream_t);
+template void copy_cols<double, float>(const double*, int64_t, float*, int64_t, int64_t, int, hipStream_t);
+
+}  // namespace trbl

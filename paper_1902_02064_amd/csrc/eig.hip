@@ -1,0 +1,418 @@
+// Symmetric eigensolver for the small projected matrix T of TRBL (Alg. 4:
+// "diagonalise T^(k)"; restart equations of Sec. 3.4), FP64, one workgroup.
+//
+//   1. Householder reduction to tridiagonal form (A = Q Tri Q^T), reflectors kept;
+//   2. eigenvalues by Sturm-sequence bisection (one thread per wanted index);
+//   3. eigenvectors of Tri by inverse iteration with a pivoted LU of (Tri - lambda I);
+//      eigenvalues closer than 1e-3 ||T|| form a cluster whose vectors are
+//      orthogonalised against the earlier members at every iteration;
+//   4. back-transformation U = Q Z.
+// Textbook methods (Householder; Sturm-sequence bisection; inverse iteration),
+// written for this library.
+#include <cfloat>
+
+#include "dense.h"
+
+namespace trbl {
+
+constexpr int EIG_THREADS = 1024;
+constexpr int EIG_NMAX = 1024;
+
+__device__ static double block_sum(double v, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  const int nw = blockDim.x >> 6;
+  for (int w = 0; w < nw; w++) s += red[w];
+  return s;
+}
+
+__device__ static uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// number of eigenvalues of the tridiagonal (d, e2 = squared off-diagonal) below x
+__device__ static int sturm(const double* d, const double* e2, int n, double x, double pivmin) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (fabs(q) <= pivmin) q = -pivmin;
+  if (q < 0.0) cnt++;
+  for (int i = 1; i < n; i++) {
+    q = d[i] - x - e2[i - 1] / q;
+    if (fabs(q) <= pivmin) q = -pivmin;
+    if (q < 0.0) cnt++;
+  }
+  return cnt;
+}
+
+__global__ __launch_bounds__(EIG_THREADS) void symeig_kernel(const double* __restrict__ T, int ldt, int n, int nvec,
+                                                             double* __restrict__ theta, double* __restrict__ U,
+                                                             int ldu, double* __restrict__ A, double* __restrict__ Z,
+                                                             double* __restrict__ LU) {
+  __shared__ double d[EIG_NMAX], e[EIG_NMAX], e2[EIG_NMAX], vv[EIG_NMAX], pw[EIG_NMAX], lam[EIG_NMAX];
+  __shared__ int cstart[EIG_NMAX + 1];
+  __shared__ int ncl;
+  __shared__ double red[32], wlo[16], whi[16], wnm[16];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nwave = nthr >> 6;
+
+  for (int64_t q = tid; q < (int64_t)n * n; q += nthr) A[q] = T[(q / n) * ldt + q % n];
+  __syncthreads();
+
+  // ---- 1. Householder tridiagonalisation (lower); reflector k is stored in row k of A
+  for (int k = 0; k + 2 < n; k++) {
+    const int len = n - k - 1;
+    const double* row = A + (int64_t)k * n + k + 1;
+    double s = 0.0;
+    for (int i = tid; i < len; i += nthr) s += row[i] * row[i];
+    const double s2 = block_sum(s, red);
+    const double x0 = row[0];
+    const double sigma = sqrt(s2);
+    if (tid == 0) d[k] = A[(int64_t)k * n + k];
+    if (sigma == 0.0) {
+      __syncthreads();
+      if (tid == 0) e[k] = 0.0;
+      for (int i = tid; i < len; i += nthr) A[(int64_t)k * n + k + 1 + i] = 0.0;
+      __syncthreads();
+      continue;
+    }
+    const double alpha = (x0 > 0.0) ? -sigma : sigma;
+    const double vn = sqrt(s2 - x0 * x0 + (x0 - alpha) * (x0 - alpha));
+    for (int i = tid; i < len; i += nthr) vv[i] = (i == 0 ? (x0 - alpha) : row[i]) / vn;
+    if (tid == 0) e[k] = alpha;
+    __syncthreads();
+    for (int i = wave; i < len; i += nwave) {  // p = A_sub v, one wave per row
+      const double* ar = A + (int64_t)(k + 1 + i) * n + k + 1;
+      double t = 0.0;
+      for (int j = lane; j < len; j += 64) t += ar[j] * vv[j];
+      for (int o = 32; o > 0; o >>= 1) t += __shfl_down(t, o, 64);
+      if (lane == 0) pw[i] = t;
+    }
+    __syncthreads();
+    double kp = 0.0;
+    for (int i = tid; i < len; i += nthr) kp += vv[i] * pw[i];
+    const double K = block_sum(kp, red);
+    for (int i = tid; i < len; i += nthr) pw[i] = 2.0 * pw[i] - 2.0 * K * vv[i];
+    __syncthreads();
+    for (int64_t q = tid; q < (int64_t)len * len; q += nthr) {
+      const int i = (int)(q / len), j = (int)(q % len);
+      A[(int64_t)(k + 1 + i) * n + k + 1 + j] -= vv[i] * pw[j] + pw[i] * vv[j];
+    }
+    for (int i = tid; i < len; i += nthr) A[(int64_t)k * n + k + 1 + i] = vv[i];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (n >= 2) {
+      d[n - 2] = A[(int64_t)(n - 2) * n + n - 2];
+      e[n - 2] = A[(int64_t)(n - 1) * n + n - 2];
+    }
+    d[n - 1] = A[(int64_t)(n - 1) * n + n - 1];
+    e[n - 1] = 0.0;
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += nthr) e2[i] = e[i] * e[i];
+  // Gershgorin interval and a norm bound
+  double glo = 1e300, ghi = -1e300, gn = 0.0;
+  for (int i = tid; i < n; i += nthr) {
+    const double r = fabs(e[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0);
+    glo = fmin(glo, d[i] - r);
+    ghi = fmax(ghi, d[i] + r);
+    gn = fmax(gn, fabs(d[i]) + r);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    glo = fmin(glo, __shfl_down(glo, o, 64));
+    ghi = fmax(ghi, __shfl_down(ghi, o, 64));
+    gn = fmax(gn, __shfl_down(gn, o, 64));
+  }
+  if (lane == 0) {
+    wlo[wave] = glo;
+    whi[wave] = ghi;
+    wnm[wave] = gn;
+  }
+  __syncthreads();
+  glo = 1e300;
+  ghi = -1e300;
+  gn = 0.0;
+  for (int w = 0; w < nwave; w++) {
+    glo = fmin(glo, wlo[w]);
+    ghi = fmax(ghi, whi[w]);
+    gn = fmax(gn, wnm[w]);
+  }
+  const double tnorm = fmax(gn, DBL_MIN);
+  const double pivmin = DBL_MIN * fmax(1.0, tnorm * tnorm);
+  glo -= 2.0 * DBL_EPSILON * tnorm * n + pivmin;
+  ghi += 2.0 * DBL_EPSILON * tnorm * n + pivmin;
+
+  // ---- 2. bisection: thread t < nvec finds eigenvalue t; thread nvec finds the largest
+  const int want = (tid < nvec) ? tid : ((tid == nvec && nvec < n) ? n - 1 : -1);
+  if (want >= 0) {
+    double lo = glo, hi = ghi;
+    for (int it = 0; it < 200; it++) {
+      const double mid = 0.5 * (lo + hi);
+      if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + 2.0 * pivmin || mid == lo || mid == hi) break;
+      if (sturm(d, e2, n, mid, pivmin) > want) hi = mid;
+      else lo = mid;
+    }
+    const double l = 0.5 * (lo + hi);
+    if (want < n) lam[want] = l;
+    theta[want] = l;
+  }
+  __syncthreads();
+
+  // ---- 3. clusters of close eigenvalues among the nvec lowest
+  if (tid == 0) {
+    const double gap = 1e-3 * tnorm;
+    int c = 0;
+    cstart[0] = 0;
+    for (int j = 1; j < nvec; j++)
+      if (lam[j] - lam[j - 1] > gap) cstart[++c] = j;
+    ncl = c + 1;
+    cstart[ncl] = nvec;
+  }
+  __syncthreads();
+  // inverse iteration: thread c handles cluster c sequentially.
+  // LU layout: array q, entry i of vector j at LU[(q * n + i) * nvec + j] (coalesced over j).
+  for (int c = tid; c < ncl; c += nthr) {
+    for (int j = cstart[c]; j < cstart[c + 1]; j++) {
+      double* dl = LU + (0 * (int64_t)n) * nvec + j;
+      double* dd = LU + (1 * (int64_t)n) * nvec + j;
+      double* du = LU + (2 * (int64_t)n) * nvec + j;
+      double* du2 = LU + (3 * (int64_t)n) * nvec + j;
+      double* pv = LU + (4 * (int64_t)n) * nvec + j;
+#define AT(p, i) (p)[(int64_t)(i) * nvec]
+      const double lm = lam[j];
+      for (int i = 0; i < n; i++) {
+        AT(dd, i) = d[i] - lm;
+        AT(du, i) = e[i];
+        AT(dl, i) = e[i];
+        AT(du2, i) = 0.0;
+        AT(pv, i) = 0.0;
+      }
+      // pivoted LU of the tridiagonal (Tri - lambda I)
+      for (int i = 0; i + 1 < n; i++) {
+        const double a = AT(dd, i), b = AT(dl, i);
+        if (fabs(a) >= fabs(b)) {
+          const double f = (a != 0.0) ? b / a : 0.0;
+          AT(dl, i) = f;
+          AT(dd, i + 1) -= f * AT(du, i);
+          AT(du2, i) = 0.0;
+        } else {
+          const double f = a / b;
+          AT(dd, i) = b;
+          AT(dl, i) = f;
+          const double t = AT(du, i);
+          AT(du, i) = AT(dd, i + 1);
+          AT(dd, i + 1) = t - f * AT(dd, i + 1);
+          if (i + 2 < n) {
+            AT(du2, i) = AT(du, i + 1);
+            AT(du, i + 1) = -f * AT(du2, i);
+          } else {
+            AT(du2, i) = 0.0;
+          }
+          AT(pv, i) = 1.0;
+        }
+      }
+      const double tiny = DBL_EPSILON * tnorm;
+      for (int i = 0; i < n; i++)
+        if (fabs(AT(dd, i)) < tiny) AT(dd, i) = (AT(dd, i) < 0.0) ? -tiny : tiny;
+      double* z = Z + j;  // column j of Z, stride nvec
+      uint64_t h = mix64(0x5D0C5EEDull + (uint64_t)j * 1315423911ull);
+      for (int i = 0; i < n; i++) {
+        h = mix64(h + i);
+        AT(z, i) = ((double)(h >> 11) * (1.0 / 9007199254740992.0)) - 0.5;
+      }
+      for (int it = 0; it < 4; it++) {
+        for (int i = 0; i + 1 < n; i++) {  // forward: P and L
+          if (AT(pv, i) != 0.0) {
+            const double t = AT(z, i);
+            AT(z, i) = AT(z, i + 1);
+            AT(z, i + 1) = t;
+          }
+          AT(z, i + 1) -= AT(dl, i) * AT(z, i);
+        }
+        AT(z, n - 1) /= AT(dd, n - 1);  // backward: U
+        if (n >= 2) AT(z, n - 2) = (AT(z, n - 2) - AT(du, n - 2) * AT(z, n - 1)) / AT(dd, n - 2);
+        for (int i = n - 3; i >= 0; i--)
+          AT(z, i) = (AT(z, i) - AT(du, i) * AT(z, i + 1) - AT(du2, i) * AT(z, i + 2)) / AT(dd, i);
+        for (int pass = 0; pass < 2; pass++) {  // against earlier cluster members
+          for (int q = cstart[c]; q < j; q++) {
+            const double* y = Z + q;
+            double s = 0.0;
+            for (int i = 0; i < n; i++) s += AT(y, i) * AT(z, i);
+            for (int i = 0; i < n; i++) AT(z, i) -= s * AT(y, i);
+          }
+        }
+        double nr = 0.0;
+        for (int i = 0; i < n; i++) nr += AT(z, i) * AT(z, i);
+        nr = 1.0 / sqrt(nr);
+        for (int i = 0; i < n; i++) AT(z, i) *= nr;
+      }
+#undef AT
+    }
+  }
+  __syncthreads();
+
+  // ---- 4. back-transformation U = H_0 H_1 ... H_{n-3} Z (apply reflectors last to first)
+  for (int k = n - 3; k >= 0; k--) {
+    const int len = n - k - 1;
+    for (int i = tid; i < len; i += nthr) vv[i] = A[(int64_t)k * n + k + 1 + i];
+    __syncthreads();
+    for (int j = tid; j < nvec; j += nthr) {
+      double s = 0.0;
+      for (int i = 0; i < len; i++) s += vv[i] * Z[(int64_t)(k + 1 + i) * nvec + j];
+      s *= 2.0;
+      for (int i = 0; i < len; i++) Z[(int64_t)(k + 1 + i) * nvec + j] -= s * vv[i];
+    }
+    __syncthreads();
+  }
+  for (int64_t q = tid; q < (int64_t)n * nvec; q += nthr) U[(q / nvec) * ldu + q % nvec] = Z[q];
+}
+
+void symeig(const double* T, int ldt, int n, int nvec, double* theta, double* U, int ldu, EigWork& w, bool orth,
+            hipStream_t st) {
+  TRBL_REQUIRE(n >= 1 && n <= EIG_NMAX && nvec >= 1 && nvec <= n, TRBL_E_INVALID, "eigensolver size out of range");
+  (void)orth;
+  w.a.alloc((size_t)n * n * sizeof(double));
+  w.z.alloc((size_t)n * nvec * sizeof(double));
+  w.lu.alloc((size_t)5 * n * nvec * sizeof(double));
+  hipLaunchKernelGGL(symeig_kernel, dim3(1), dim3(EIG_THREADS), 0, st, T, ldt, n, nvec, theta, U, ldu, w.a.as<double>(),
+                     w.z.as<double>(), w.lu.as<double>());
+  TRBL_HIP(hipGetLastError());
+}
+
+}  // namespace trbl
+
+namespace trbl {
+
+// M = L^-1 S L^-T with G = L L^T (one workgroup, n <= 1024)
+__global__ __launch_bounds__(1024) void gen_reduce_kernel(const double* __restrict__ S, const double* __restrict__ G,
+                                                          int n, double* __restrict__ M, double* __restrict__ L,
+                                                          double* __restrict__ Li, int* status) {
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  __shared__ int bad;
+  if (tid == 0) bad = 0;
+  for (int64_t q = tid; q < (int64_t)n * n; q += nthr) {
+    const int i = (int)(q / n), j = (int)(q % n);
+    L[q] = (j <= i) ? 0.5 * (G[q] + G[(int64_t)j * n + i]) : 0.0;
+  }
+  __syncthreads();
+  // left-looking Cholesky, lower triangular L
+  for (int k = 0; k < n; k++) {
+    if (tid == 0) {
+      double p = L[(int64_t)k * n + k];
+      for (int q = 0; q < k; q++) p -= L[(int64_t)k * n + q] * L[(int64_t)k * n + q];
+      if (!(p > 0.0)) {
+        bad = 1;
+        p = 1e-300;
+      }
+      L[(int64_t)k * n + k] = sqrt(p);
+    }
+    __syncthreads();
+    const double lkk = L[(int64_t)k * n + k];
+    for (int i = k + 1 + tid; i < n; i += nthr) {
+      double s = L[(int64_t)i * n + k];
+      for (int q = 0; q < k; q++) s -= L[(int64_t)i * n + q] * L[(int64_t)k * n + q];
+      L[(int64_t)i * n + k] = s / lkk;
+    }
+    __syncthreads();
+  }
+  // Li = L^-1 (lower), one thread per column
+  for (int j = tid; j < n; j += nthr) {
+    for (int i = 0; i < n; i++) Li[(int64_t)i * n + j] = 0.0;
+    Li[(int64_t)j * n + j] = 1.0 / L[(int64_t)j * n + j];
+    for (int i = j + 1; i < n; i++) {
+      double s = 0.0;
+      for (int q = j; q < i; q++) s += L[(int64_t)i * n + q] * Li[(int64_t)q * n + j];
+      Li[(int64_t)i * n + j] = -s / L[(int64_t)i * n + i];
+    }
+  }
+  __syncthreads();
+  // M = Li S Li^T, via P = Li S (stored in L) then M = P Li^T
+  for (int64_t q = tid; q < (int64_t)n * n; q += nthr) {
+    const int i = (int)(q / n), j = (int)(q % n);
+    double s = 0.0;
+    for (int t = 0; t <= i; t++) s += Li[(int64_t)i * n + t] * 0.5 * (S[(int64_t)t * n + j] + S[(int64_t)j * n + t]);
+    L[q] = s;
+  }
+  __syncthreads();
+  for (int64_t q = tid; q < (int64_t)n * n; q += nthr) {
+    const int i = (int)(q / n), j = (int)(q % n);
+    double s = 0.0;
+    for (int t = 0; t <= j; t++) s += L[(int64_t)i * n + t] * Li[(int64_t)j * n + t];
+    M[q] = s;
+  }
+  __syncthreads();
+  for (int64_t q = tid; q < (int64_t)n * n; q += nthr) {
+    const int i = (int)(q / n), j = (int)(q % n);
+    if (j < i) M[q] = M[(int64_t)j * n + i] = 0.5 * (M[q] + M[(int64_t)j * n + i]);
+  }
+  if (tid == 0) status[0] = bad;
+}
+
+__global__ void gen_back_kernel(const double* Li, const double* Yp, int ldp, int n, int nv, double* Y, int ldy) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= (int64_t)n * nv) return;
+  const int i = (int)(q / nv), j = (int)(q % nv);
+  double s = 0.0;
+  for (int t = i; t < n; t++) s += Li[(int64_t)t * n + i] * Yp[(int64_t)t * ldp + j];  // (L^-T)_{it} = Li_{ti}
+  Y[(int64_t)i * ldy + j] = s;
+}
+
+__global__ void reduce_partials_kernel_eig(const double* part, int G, int len, double* out) {
+  const int k = threadIdx.x;
+  if (k >= len) return;
+  double s = 0.0;
+  for (int g = 0; g < G; g++) s += part[(int64_t)g * len + k];
+  out[k] = s;
+}
+
+__global__ void resid_cols_kernel(const double* W, int64_t ldw, const double* X, int64_t ldx, const double* theta,
+                                  int ncol, int64_t D, int64_t rows_per, double* part) {
+  const int c = threadIdx.x % 64;
+  const int rsub = threadIdx.x / 64;
+  __shared__ double acc[4][64];
+  double s = 0.0;
+  const int64_t r0 = blockIdx.x * rows_per, r1 = min(D, r0 + rows_per);
+  if (c < ncol)
+    for (int64_t r = r0 + rsub; r < r1; r += 4) {
+      const double x = W[r * ldw + c] - theta[c] * X[r * ldx + c];
+      s += x * x;
+    }
+  acc[rsub][c] = s;
+  __syncthreads();
+  if (rsub == 0 && c < ncol) part[(int64_t)blockIdx.x * ncol + c] = acc[0][c] + acc[1][c] + acc[2][c] + acc[3][c];
+}
+
+void gen_reduce(const double* S, const double* G, int n, double* M, double* Linv, int* status, hipStream_t st) {
+  static thread_local DevBuf Lb;
+  Lb.alloc((size_t)n * n * sizeof(double));
+  hipLaunchKernelGGL(gen_reduce_kernel, dim3(1), dim3(1024), 0, st, S, G, n, M, Lb.as<double>(), Linv, status);
+  TRBL_HIP(hipGetLastError());
+}
+
+void gen_back(const double* Linv, const double* Yp, int ldp, int n, int nv, double* Y, int ldy, hipStream_t st) {
+  const int64_t tot = (int64_t)n * nv;
+  hipLaunchKernelGGL(gen_back_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Linv, Yp, ldp, n, nv, Y,
+                     ldy);
+  TRBL_HIP(hipGetLastError());
+}
+
+void resid_cols(const double* W, int64_t ldw, const double* X, int64_t ldx, const double* theta, int ncol, int64_t D,
+                double* out, Scratch& s, hipStream_t st) {
+  TRBL_REQUIRE(ncol <= 64, TRBL_E_INVALID, "resid_cols: at most 64 columns per call");
+  int G = (int)std::min<int64_t>(1024, std::max<int64_t>(1, D / 1024));
+  const int64_t rows_per = (D + G - 1) / G;
+  G = (int)((D + rows_per - 1) / rows_per);
+  double* part = s.partials((size_t)G * ncol);
+  hipLaunchKernelGGL(resid_cols_kernel, dim3(G), dim3(256), 0, st, W, ldw, X, ldx, theta, ncol, D, rows_per, part);
+  hipLaunchKernelGGL(reduce_partials_kernel_eig, dim3(1), dim3(64), 0, st, part, G, ncol, out);
+  TRBL_HIP(hipGetLastError());
+}
+
+}  // namespace trbl

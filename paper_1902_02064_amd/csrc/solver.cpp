@@ -1,6 +1,274 @@
-#include "internal.h"
+// Thick-restart block Lanczos driver (Alg. 4 and the restart equations of Sec. 3.4).
+//
+// Per block iteration k (all vector work on one HIP stream, all D-length data in HBM):
+//   W := H V_k                           on-the-fly block H.V (hv.hip)
+//   C1 := Q^T W,  alpha_k := sym(V_k^T W) (rows of C1 belonging to V_k)
+//   W -= Q C1 ; C2 := Q^T W ; W -= Q C2   classical Gram-Schmidt twice against every
+//                                         stored vector v_1 .. v_{k_x + p k}
+//   V_{k+1} beta_k := QR(W)               Cholesky QR, twice (beta = R2 R1, diag > 0)
+//   T blocks (k,k) = alpha_k, (k+1,k) = beta_k, (k,k+1) = beta_k^T
+//   diagonalise T^(k); rho_i = || beta_k U[last block rows, i] ||
+// stop when rho_i <= tol * max|theta| for the n_eig lowest; restart when the next
+// block would exceed l_m stored vectors:
+//   v_k := sum_j v_j U_jk (k <= l_s),  V_1 := V_{k+1},  r := beta_k U[last block, 1:l_s],
+//   T := [diag(theta_1..l_s) r^T ; r .],  k_x := l_s.
+// Mixed precision: the stored vectors Q and H.V are FP32; projections, the
+// orthogonalised W, QR, T and its eigenproblem are FP64; at the end an FP64
+// Rayleigh-Ritz step on the Ritz vectors refines the eigenvalues.
+#include <chrono>
+#include <cmath>
+
+#include "dense.h"
+
 namespace trbl {
-int solve(const Model&, const trbl_opts&, double*, void*, trbl_info*) {
-  throw Error{TRBL_E_STATE, "solver not built yet"};
+
+namespace {
+
+struct Events {
+  hipEvent_t e[6];
+  Events() {
+    for (auto& x : e) TRBL_HIP(hipEventCreate(&x));
+  }
+  ~Events() {
+    for (auto& x : e) (void)hipEventDestroy(x);
+  }
+  double ms(int a, int b) const {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, e[a], e[b]) != hipSuccess) return 0.0;
+    return t * 1e-3;
+  }
+};
+
+int64_t round4(int64_t x) { return (x + 3) / 4 * 4; }
+
+}  // namespace
+
+template <class TQ>
+static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evecs, trbl_info* info) {
+  constexpr bool mixed = sizeof(TQ) == 4;
+  const int64_t D = m.dim;
+  const int nb = o.nb, neig = o.n_eig, ls = o.l_s, lm = o.l_m;
+  TRBL_REQUIRE(m.has_h, TRBL_E_STATE, "no Hamiltonian set");
+  TRBL_REQUIRE(nb >= 1 && nb <= 64, TRBL_E_INVALID, "nb must be 1..64");
+  TRBL_REQUIRE(neig >= 1 && neig <= ls, TRBL_E_INVALID, "need 1 <= n_eig <= l_s");
+  TRBL_REQUIRE(ls + 2 * nb <= lm && (int64_t)lm <= D, TRBL_E_INVALID, "need l_s + 2 nb <= l_m <= D");
+  TRBL_REQUIRE(lm <= 768, TRBL_E_INVALID, "l_m above 768 is not supported");
+  TRBL_REQUIRE(o.tol > 0.0 && o.max_iter >= 1, TRBL_E_INVALID, "bad tol or max_iter");
+  hipStream_t st = (hipStream_t)o.stream;
+  // an FP32 residual cannot fall far below the FP32 rounding of H.V: floor the tolerance
+  const double tol = mixed ? std::max(o.tol, 1e-5) : o.tol;
+  const auto t_begin = std::chrono::steady_clock::now();
+
+  const int64_t ldq = round4(lm);
+  const int ldu = std::max(ls, neig);
+  DevBuf Qb, Wb, W32b, Tb, C1b, C2b, Rb, thb, Ub, rhob, stb;
+  Qb.alloc((size_t)D * ldq * sizeof(TQ));
+  Wb.alloc((size_t)D * nb * sizeof(double));
+  if (mixed) W32b.alloc((size_t)D * nb * sizeof(float));
+  Tb.alloc((size_t)lm * lm * sizeof(double));
+  C1b.alloc((size_t)lm * nb * sizeof(double));
+  C2b.alloc((size_t)lm * nb * sizeof(double));
+  Rb.alloc((size_t)5 * nb * nb * sizeof(double));
+  thb.alloc((size_t)lm * sizeof(double));
+  Ub.alloc((size_t)lm * ldu * sizeof(double));
+  rhob.alloc((size_t)std::max(neig, 64) * sizeof(double));
+  stb.alloc(4 * sizeof(int));
+  TQ* Q = Qb.as<TQ>();
+  double* W = Wb.as<double>();
+  float* W32 = W32b.as<float>();
+  double* T = Tb.as<double>();
+  double* C1 = C1b.as<double>();
+  double* C2 = C2b.as<double>();
+  double* R1 = Rb.as<double>();
+  double* R1i = R1 + nb * nb;
+  double* R2 = R1i + nb * nb;
+  double* R2i = R2 + nb * nb;
+  double* beta = R2i + nb * nb;
+  double* theta = thb.as<double>();
+  double* U = Ub.as<double>();
+  double* rho = rhob.as<double>();
+  int* status = stb.as<int>();
+  Scratch sc;
+  EigWork ew;
+  Events ev;
+
+  // ---- start block V_1 (orthonormalised by Cholesky QR twice)
+  if (o.v0)
+    copy_cols<TQ, TQ>(static_cast<const TQ*>(o.v0), nb, Q, ldq, D, nb, st);
+  else
+    random_block<TQ>(Q, ldq, D, nb, o.seed, st);
+  tn<TQ, TQ>(Q, ldq, nb, Q, ldq, nb, D, C1, sc, st);
+  chol(C1, 1, nb, R1, R1i, nullptr, nullptr, status, st);
+  apply_small<TQ, double>(Q, ldq, R1i, W, nb, nb, D, true, sc, st);
+  chol(sc.last_part, sc.last_G, nb, R2, R2i, nullptr, nullptr, status + 1, st);
+  apply_small<double, TQ>(W, nb, R2i, Q, ldq, nb, D, false, sc, st);
+  TRBL_HIP(hipMemsetAsync(T, 0, sizeof(double) * (size_t)lm * lm, st));
+  int sth[4] = {0, 0, 0, 0};
+  TRBL_HIP(hipMemcpyAsync(sth, status, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  TRBL_HIP(hipStreamSynchronize(st));
+  TRBL_REQUIRE(sth[0] == 0 && sth[1] == 0, TRBL_E_BREAKDOWN, "start block is rank deficient");
+
+  int kx = 0, k = 0, it = 0, restarts = 0, mcur = 0;
+  double hnorm = 0.0;
+  std::vector<double> th(neig), rh(neig);
+  double t_hv = 0, t_orth = 0, t_qr = 0, t_eig = 0, t_rst = 0;
+  bool converged = false;
+  int nchk = 0;
+  for (it = 1; it <= o.max_iter; it++) {
+    k++;
+    const int c0 = kx + (k - 1) * nb;
+    mcur = c0 + nb;
+    TRBL_HIP(hipEventRecord(ev.e[0], st));
+    // W := H V_k
+    void* Wh = mixed ? (void*)W32 : (void*)W;
+    launch_apply(m, mixed ? TRBL_MIXED : TRBL_FP64, nb, Q + c0, ldq, Wh, nb, st);
+    TRBL_HIP(hipEventRecord(ev.e[1], st));
+    // projections and block classical Gram-Schmidt, twice
+    if (mixed) {
+      tn<float, float>((const float*)Q, ldq, mcur, W32, nb, nb, D, C1, sc, st);
+      t_alpha(T, lm, c0, nb, C1, st);
+      update<float, float>((const float*)Q, ldq, mcur, C1, W32, nb, W, nb, nb, D, 1, C2, sc, st);
+      update<float, double>((const float*)Q, ldq, mcur, C2, W, nb, W, nb, nb, D, 2, nullptr, sc, st);
+    } else {
+      tn<double, double>((const double*)Q, ldq, mcur, W, nb, nb, D, C1, sc, st);
+      t_alpha(T, lm, c0, nb, C1, st);
+      update<double, double>((const double*)Q, ldq, mcur, C1, W, nb, W, nb, nb, D, 1, C2, sc, st);
+      update<double, double>((const double*)Q, ldq, mcur, C2, W, nb, W, nb, nb, D, 2, nullptr, sc, st);
+    }
+    TRBL_HIP(hipEventRecord(ev.e[2], st));
+    // V_{k+1} beta_k := QR(W): Cholesky QR twice
+    chol(sc.last_part, sc.last_G, nb, R1, R1i, nullptr, nullptr, status, st);
+    apply_small<double, double>(W, nb, R1i, W, nb, nb, D, true, sc, st);
+    chol(sc.last_part, sc.last_G, nb, R2, R2i, R1, beta, status + 1, st);
+    apply_small<double, TQ>(W, nb, R2i, Q + mcur, ldq, nb, D, false, sc, st);
+    t_beta(T, lm, c0, mcur, nb, beta, st);
+    TRBL_HIP(hipEventRecord(ev.e[3], st));
+    // diagonalise T^(k)
+    const bool restart_next = mcur + 2 * nb > lm;
+    const int nvec = restart_next ? ls : std::min(neig, mcur);
+    symeig(T, lm, mcur, nvec, theta, U, ldu, ew, restart_next, st);
+    nchk = std::min(neig, mcur);
+    resid(beta, nb, U, ldu, mcur, nchk, rho, st);
+    TRBL_HIP(hipEventRecord(ev.e[4], st));
+    TRBL_HIP(hipMemcpyAsync(th.data(), theta, nchk * sizeof(double), hipMemcpyDeviceToHost, st));
+    double tmax = 0.0;
+    TRBL_HIP(hipMemcpyAsync(&tmax, theta + mcur - 1, sizeof(double), hipMemcpyDeviceToHost, st));
+    TRBL_HIP(hipMemcpyAsync(rh.data(), rho, nchk * sizeof(double), hipMemcpyDeviceToHost, st));
+    TRBL_HIP(hipMemcpyAsync(sth, status, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    TRBL_HIP(hipStreamSynchronize(st));
+    t_hv += ev.ms(0, 1);
+    t_orth += ev.ms(1, 2);
+    t_qr += ev.ms(2, 3);
+    t_eig += ev.ms(3, 4);
+    TRBL_REQUIRE(sth[0] == 0 && sth[1] == 0, TRBL_E_BREAKDOWN,
+                 "block Lanczos breakdown: new block is numerically rank deficient");
+    hnorm = std::max(hnorm, std::max(std::fabs(th[0]), std::fabs(tmax)));
+    bool ok = nchk == neig;
+    for (int i = 0; ok && i < nchk; i++) ok = rh[i] <= tol * hnorm;
+    if (ok) {
+      converged = true;
+      break;
+    }
+    if (restart_next && it < o.max_iter) {
+      TRBL_HIP(hipEventRecord(ev.e[4], st));
+      rowgemm<TQ, TQ>(Q, ldq, mcur, U, ldu, ls, Q, ldq, D, mcur, ls, nb, st);
+      t_restart(T, lm, lm, theta, ls, beta, nb, U, ldu, mcur, st);
+      TRBL_HIP(hipEventRecord(ev.e[5], st));
+      TRBL_HIP(hipEventSynchronize(ev.e[5]));
+      t_rst += ev.ms(4, 5);
+      kx = ls;
+      k = 0;
+      restarts++;
+    }
+  }
+  if (it > o.max_iter) it = o.max_iter;
+
+  // ---- results: Ritz values and (optionally) Ritz vectors X = Q U[:, :n_eig]
+  double t_refine = 0.0;
+  std::vector<double> res(rh.begin(), rh.begin() + nchk);
+  for (int i = 0; i < neig; i++) evals[i] = i < nchk ? th[i] : NAN;
+  if (!mixed || !o.refine) {
+    if (evecs) rowgemm<TQ, double>(Q, ldq, mcur, U, ldu, neig, static_cast<double*>(evecs), neig, D, -1, 0, 0, st);
+  } else {
+    // FP64 Rayleigh-Ritz on span(X), X = Q U[:, :n_eig] stored in place in Q's first n_eig columns
+    TRBL_HIP(hipEventRecord(ev.e[0], st));
+    TRBL_REQUIRE(neig <= 208, TRBL_E_INVALID, "refinement supports n_eig <= 208");
+    rowgemm<TQ, TQ>(Q, ldq, mcur, U, ldu, neig, Q, ldq, D, -1, 0, 0, st);
+    const int cw = (int)std::max<int64_t>(1, std::min<int64_t>(32, (int64_t)(8e9 / (16.0 * D))));
+    DevBuf Xc, Hc, Sb, Gb, Mb, Lb, Yb, Yp, tmp, th2, st2;
+    Xc.alloc((size_t)D * cw * sizeof(double));
+    Hc.alloc((size_t)D * cw * sizeof(double));
+    Sb.alloc((size_t)neig * neig * sizeof(double));
+    Gb.alloc((size_t)neig * neig * sizeof(double));
+    Mb.alloc((size_t)neig * neig * sizeof(double));
+    Lb.alloc((size_t)neig * neig * sizeof(double));
+    Yb.alloc((size_t)neig * neig * sizeof(double));
+    Yp.alloc((size_t)neig * neig * sizeof(double));
+    tmp.alloc((size_t)neig * cw * sizeof(double));
+    th2.alloc((size_t)neig * sizeof(double));
+    st2.alloc(sizeof(int));
+    double* S = Sb.as<double>();
+    double* G = Gb.as<double>();
+    for (int c = 0; c < neig; c += cw) {
+      const int w = std::min(cw, neig - c);
+      copy_cols<TQ, double>(Q + c, ldq, Xc.as<double>(), w, D, w, st);
+      launch_apply(m, TRBL_FP64, w, Xc.as<double>(), w, Hc.as<double>(), w, st);
+      tn<TQ, double>(Q, ldq, neig, Hc.as<double>(), w, w, D, tmp.as<double>(), sc, st);
+      copy_cols<double, double>(tmp.as<double>(), w, S + c, neig, neig, w, st);
+      tn<TQ, double>(Q, ldq, neig, Xc.as<double>(), w, w, D, tmp.as<double>(), sc, st);
+      copy_cols<double, double>(tmp.as<double>(), w, G + c, neig, neig, w, st);
+    }
+    gen_reduce(S, G, neig, Mb.as<double>(), Lb.as<double>(), st2.as<int>(), st);
+    symeig(Mb.as<double>(), neig, neig, neig, th2.as<double>(), Yp.as<double>(), neig, ew, false, st);
+    gen_back(Lb.as<double>(), Yp.as<double>(), neig, neig, neig, Yb.as<double>(), neig, st);
+    int gst = 0;
+    TRBL_HIP(hipMemcpyAsync(evals, th2.as<double>(), neig * sizeof(double), hipMemcpyDeviceToHost, st));
+    TRBL_HIP(hipMemcpyAsync(&gst, st2.as<int>(), sizeof(int), hipMemcpyDeviceToHost, st));
+    if (evecs) {
+      double* X = static_cast<double*>(evecs);
+      rowgemm<TQ, double>(Q, ldq, neig, Yb.as<double>(), neig, neig, X, neig, D, -1, 0, 0, st);
+      // residual norms of the refined pairs in FP64
+      DevBuf rs;
+      rs.alloc((size_t)neig * sizeof(double));
+      for (int c = 0; c < neig; c += cw) {
+        const int w = std::min(std::min(cw, 64), neig - c);
+        launch_apply(m, TRBL_FP64, w, X + c, neig, Hc.as<double>(), w, st);
+        resid_cols(Hc.as<double>(), w, X + c, neig, th2.as<double>() + c, w, D, rs.as<double>() + c, sc, st);
+      }
+      TRBL_HIP(hipMemcpyAsync(res.data(), rs.as<double>(), neig * sizeof(double), hipMemcpyDeviceToHost, st));
+      TRBL_HIP(hipStreamSynchronize(st));
+      for (auto& x : res) x = std::sqrt(x);
+    }
+    TRBL_HIP(hipEventRecord(ev.e[1], st));
+    TRBL_HIP(hipStreamSynchronize(st));
+    TRBL_REQUIRE(gst == 0, TRBL_E_BREAKDOWN, "refinement Gram matrix not positive definite");
+    t_refine = ev.ms(0, 1);
+  }
+  TRBL_HIP(hipStreamSynchronize(st));
+  if (info) {
+    info->iterations = it;
+    info->restarts = restarts;
+    info->breakdowns = 0;
+    int nconv = 0;
+    for (int i = 0; i < nchk; i++) nconv += rh[i] <= tol * hnorm;
+    info->n_converged = nconv;
+    info->t_hv = t_hv;
+    info->t_orth = t_orth;
+    info->t_qr = t_qr;
+    info->t_eig = t_eig;
+    info->t_restart = t_rst;
+    info->t_refine = t_refine;
+    info->t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_begin).count();
+    if (info->resid)
+      for (int i = 0; i < neig; i++) info->resid[i] = i < (int)res.size() ? res[i] : NAN;
+  }
+  return converged ? TRBL_OK : TRBL_NOT_CONVERGED;
 }
+
+int solve(const Model& m, const trbl_opts& o, double* evals, void* evecs, trbl_info* info) {
+  if (o.precision == TRBL_FP64) return solve_t<double>(m, o, evals, evecs, info);
+  TRBL_REQUIRE(o.precision == TRBL_MIXED, TRBL_E_INVALID, "bad precision");
+  return solve_t<float>(m, o, evals, evecs, info);
+}
+
 }  // namespace trbl

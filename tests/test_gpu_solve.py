@@ -1,0 +1,86 @@
+"""Parity of the GPU TRBL solver (trbl_solve) with the oracle (GPU)."""
+import numpy as np
+import pytest
+
+from gpu_common import pair, say
+from oracle.trbl import trbl as oracle_trbl
+from workloads import PF_ORBITS, SD_ORBITS, SD_SPE, WORKLOADS, random_block, random_tbme
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sd22():
+    w = WORKLOADS["sd22"]
+    g, o = pair(w.orbits, w.n_prot, w.n_neut, w.twoM, w.tbme(), w.spe, w.spe)
+    H = o.dense()
+    e, U = np.linalg.eigh(H)
+    return w, g, o, H, e
+
+
+def test_fp64_matches_oracle_sd22(sd22):
+    """sd shell 2+2, nb=4, 10 lowest, tol 1e-8: eigenvalues to 1e-8 relative, Ritz residuals."""
+    w, g, o, H, e = sd22
+    say("solve sd22 fp64")
+    ev, X, info = g.solve(w.nb, w.n_eig, w.l_s, w.l_m, w.tol, "fp64", vectors=True)
+    assert info.converged, info
+    assert info.restarts >= 1
+    rel = np.abs(ev - e[:w.n_eig]) / np.abs(e[:w.n_eig])
+    say("max rel err", rel.max(), "iters", info.iterations)
+    assert rel.max() <= 1e-8
+    Xh = X.cpu().numpy()
+    res = np.linalg.norm(H @ Xh - Xh * ev, axis=0)
+    assert res.max() <= 1.5 * w.tol * np.abs(e).max()
+    assert np.abs(Xh.T @ Xh - np.eye(w.n_eig)).max() < 1e-10
+
+
+def test_fp64_same_iterates_as_oracle_trbl(sd22):
+    """Same start block: the oracle's TRBL (Alg. 4) and the GPU take the same number of iterations."""
+    w, g, o, H, e = sd22
+    V1 = random_block(1000, g.dim, w.nb)
+    ev_o, _, info_o = oracle_trbl(o.apply, o.dim, V1, w.n_eig, w.l_s, w.l_m, w.tol)
+    ev_g, _, info_g = g.solve(w.nb, w.n_eig, w.l_s, w.l_m, w.tol, "fp64", v0=torch.from_numpy(V1).cuda())
+    say("iters oracle", info_o["iterations"], "gpu", info_g.iterations)
+    assert abs(info_o["iterations"] - info_g.iterations) <= 2
+    assert np.abs(ev_o - ev_g).max() <= 1e-8 * np.abs(ev_o).max()
+
+
+def test_mixed_matches_oracle_sd22(sd22):
+    """Mixed precision (FP32 vectors and H.V) with FP64 refinement: <= 1e-6 relative per eigenvalue."""
+    w, g, o, H, e = sd22
+    say("solve sd22 mixed")
+    ev, X, info = g.solve(w.nb, w.n_eig, w.l_s, w.l_m, w.tol, "mixed", vectors=True)
+    rel = np.abs(ev - e[:w.n_eig]) / np.abs(e[:w.n_eig])
+    say("mixed per-eigenvalue rel err", rel)
+    assert rel.max() <= 1e-6
+    Xh = X.cpu().numpy()
+    assert np.abs(Xh.T @ Xh - np.eye(w.n_eig)).max() < 1e-8
+
+
+@pytest.mark.parametrize("nb,ls,lm,neig", [(1, 8, 40, 6), (2, 12, 30, 8), (8, 16, 64, 10), (16, 40, 120, 30)])
+def test_block_sizes_and_restart_shapes(sd22, nb, ls, lm, neig):
+    w, g, o, H, e = sd22
+    say("solve sd22 nb", nb, ls, lm)
+    ev, _, info = g.solve(nb, neig, ls, lm, 1e-9, "fp64", seed=7)
+    assert info.converged
+    # p=1 cannot see multiplicities: compare with the distinct spectrum when nb is small
+    assert np.abs(ev - e[:neig]).max() <= 1e-8 * np.abs(e).max()
+
+
+def test_m1_companion_and_odd_space():
+    tb = random_tbme(SD_ORBITS, 1)
+    for z, n, twoM in ((2, 2, 2), (3, 2, 1)):
+        g, o = pair(SD_ORBITS, z, n, twoM, tb, SD_SPE, SD_SPE)
+        e = np.linalg.eigvalsh(o.dense())
+        ev, _, info = g.solve(4, 10, 20, 60, 1e-9, "fp64")
+        assert info.converged and np.abs(ev - e[:10]).max() <= 1e-8 * np.abs(e).max()
+
+
+def test_degenerate_spectrum_block_finds_distinct_values():
+    """SPE-only H: the ground value -15.6 is 29-fold degenerate (> nb); block Lanczos finds the
+    distinct values (in exact arithmetic at most nb copies of each)."""
+    g, o = pair(SD_ORBITS, 2, 2, 0, [], SD_SPE, SD_SPE)
+    ev, _, info = g.solve(4, 4, 12, 40, 1e-10, "fp64")
+    assert info.converged
+    assert np.allclose(ev, -15.6, atol=1e-9)
