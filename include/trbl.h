@@ -84,6 +84,8 @@ typedef struct {
   uint64_t seed;   /* seed of the random start block (splitmix64 + Box-Muller) */
   const void* v0;  /* optional device start block [D][nb] (FP64 or FP32 per precision); NULL = random */
   void* stream;    /* hipStream_t; NULL = default stream */
+  int check_every; /* diagonalise T for the convergence test every k iterations (and at every
+                      restart); 0 or 1 = every iteration, as in Alg. 4 */
 } trbl_opts;
 
 typedef struct {

@@ -34,6 +34,8 @@ def _load():
                                         P, ctypes.c_int, P]
         _lib.orc_apply_rows.restype = ctypes.c_int
         _lib.orc_num_threads.restype = ctypes.c_int
+        _lib.orc_row_nnz.argtypes = [P, i64, P, P, P, i64, ctypes.c_int, P, P, P, P, P, P, P, i64, P]
+        _lib.orc_row_nnz.restype = ctypes.c_int
     return _lib
 
 
@@ -140,6 +142,20 @@ class Model:
         if rc != 0:
             raise RuntimeError(f"orc_apply_rows failed ({rc})")
         return W
+
+    def row_nnz(self, idx=None):
+        """Non-zero count of each row (all rows by default)."""
+        lib = _load()
+        idx = np.arange(self.dim) if idx is None else idx
+        idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64))
+        out = np.zeros(len(idx), dtype=np.int64)
+        ta, tb, tc, td, th, start = self._rowterms
+        rc = lib.orc_row_nnz(_ptr(idx), len(idx), _ptr(self.words), _ptr(self.sorted), _ptr(self.sidx), self.dim,
+                             self.S, _ptr(self.e), _ptr(ta), _ptr(tb), _ptr(tc), _ptr(td), _ptr(th), _ptr(start),
+                             self.cap, _ptr(out))
+        if rc != 0:
+            raise RuntimeError(f"orc_row_nnz failed ({rc})")
+        return out
 
     def apply(self, V):
         return self.apply_rows(V, np.arange(self.dim))

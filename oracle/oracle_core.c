@@ -166,6 +166,35 @@ int orc_apply_rows(const int64_t* list, int64_t nlist, const uint64_t* words, co
     return err;
 }
 
+/* Number of non-zero elements of every listed row (structural count after merging). */
+int orc_row_nnz(const int64_t* list, int64_t nlist, const uint64_t* words, const uint64_t* sorted,
+                const int64_t* sidx, int64_t D, int S, const double* e, const int* ta, const int* tb,
+                const int* tc, const int* td, const double* th, const int64_t* start,
+                int64_t per_line_cap, int64_t* nnz) {
+    int err = 0;
+#pragma omp parallel
+    {
+        entry* buf = (entry*)malloc(sizeof(entry) * (size_t)per_line_cap);
+        if (!buf) {
+#pragma omp atomic write
+            err = -2;
+        } else {
+#pragma omp for schedule(dynamic, 256)
+            for (int64_t r = 0; r < nlist; r++) {
+                int64_t m = line_entries(0, list[r], words, sorted, sidx, D, S, e, ta, tb, tc, td, th,
+                                         start, buf, per_line_cap);
+                nnz[r] = m;
+                if (m < 0) {
+#pragma omp atomic write
+                    err = -1;
+                }
+            }
+            free(buf);
+        }
+    }
+    return err;
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
     extern int omp_get_max_threads(void);

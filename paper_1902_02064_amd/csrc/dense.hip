@@ -45,11 +45,11 @@ __device__ __forceinline__ void ld4(const T* p, int valid, double out[4]) {
 
 // ------------------------------------------------------------------ C = A^T B (partial per workgroup)
 // A: [D][lda] (m columns used), B: [D][ldb] (nb columns). part[g] is m x nb row-major.
-template <class TA, class TB>
+template <class TA, class TB, int MAXI, int MAXC>
 __global__ __launch_bounds__(512) void tn_partial_kernel(const TA* __restrict__ A, int64_t lda, int m,
                                                          const TB* __restrict__ B, int64_t ldb, int nb, int64_t D,
                                                          int64_t rows_per, double* __restrict__ part) {
-  constexpr int WAVES = 8, MAXI = 6, MAXC = 4;
+  constexpr int WAVES = 8;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int mt = (m + 15) >> 4, ct = (nb + 15) >> 4;
   d4 acc[MAXI][MAXC];
@@ -109,12 +109,12 @@ __global__ void reduce_partials_kernel(const double* __restrict__ part, int G, i
 // ------------------------------------------------------------------ Bout = Bin - A C (+ fused partial product)
 // mode 0: update only; mode 1: also part[g] += A^T Bout (m x nb); mode 2: also part[g] += Bout^T Bout (nb x nb).
 // C (m x nb, FP64) is staged in LDS, padded to 16-multiples with zeros.
-template <class TA, class TI, int WAVES>
+template <class TA, class TI, int WAVES, int MAXI, int MAXC>
 __global__ __launch_bounds__(WAVES * 64) void update_kernel(const TA* __restrict__ A, int64_t lda, int m,
                                                      const double* __restrict__ C, const TI* Bin, int64_t ldi,
                                                      double* Bout, int64_t ldo, int nb, int64_t D, int mode,
                                                      double* __restrict__ part) {
-  constexpr int ROWS = WAVES * 16, MAXI = 48 / WAVES, MAXC = 4;
+  constexpr int ROWS = WAVES * 16;
   extern __shared__ double lds[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int mt = (m + 15) >> 4, ct = (nb + 15) >> 4;
@@ -531,7 +531,24 @@ void tn(const TA* A, int64_t lda, int m, const TB* B, int64_t ldb, int nb, int64
   int64_t rows_per = ((D + G - 1) / G + 3) / 4 * 4;
   G = (int)((D + rows_per - 1) / rows_per);
   double* part = s.partials((size_t)G * m * nb);
-  hipLaunchKernelGGL((tn_partial_kernel<TA, TB>), dim3(G), dim3(512), 0, st, A, lda, m, B, ldb, nb, D, rows_per, part);
+  const int mt = (m + 15) / 16, ct = (nb + 15) / 16, mi = (mt + 7) / 8;
+#define TN_LAUNCH(MI, MC)                                                                                     \
+  hipLaunchKernelGGL((tn_partial_kernel<TA, TB, MI, MC>), dim3(G), dim3(512), 0, st, A, lda, m, B, ldb, nb, D, \
+                     rows_per, part)
+  if (ct == 1) {
+    if (mi <= 1) TN_LAUNCH(1, 1);
+    else if (mi <= 2) TN_LAUNCH(2, 1);
+    else if (mi <= 4) TN_LAUNCH(4, 1);
+    else TN_LAUNCH(6, 1);
+  } else if (ct == 2) {
+    if (mi <= 2) TN_LAUNCH(2, 2);
+    else if (mi <= 4) TN_LAUNCH(4, 2);
+    else TN_LAUNCH(6, 2);
+  } else {
+    if (mi <= 2) TN_LAUNCH(2, 4);
+    else TN_LAUNCH(6, 4);
+  }
+#undef TN_LAUNCH
   const int64_t len = (int64_t)m * nb;
   hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, part, G, len, C);
   TRBL_HIP(hipGetLastError());
@@ -548,17 +565,31 @@ void update(const TA* A, int64_t lda, int m, const double* C, const TI* Bin, int
   };
   const int waves = (shm_for(8) <= 160 * 1024 && mt <= 48) ? 8 : 4;
   const size_t shm = shm_for(waves);
-  TRBL_REQUIRE(shm <= 160 * 1024 && (mt + waves - 1) / waves <= 48 / waves, TRBL_E_INVALID,
+  TRBL_REQUIRE(shm <= 160 * 1024 && (mt + waves - 1) / waves <= (waves == 8 ? 6 : 12), TRBL_E_INVALID,
                "update tile does not fit in LDS");
   int G = grid_for(D, waves * 16 * 4, 1024);
   const int64_t plen = mode == 1 ? (int64_t)m * nb : (int64_t)nb * nb;
   double* part = mode ? s.partials((size_t)G * plen) : nullptr;
-  if (waves == 8)
-    hipLaunchKernelGGL((update_kernel<TA, TI, 8>), dim3(G), dim3(512), shm, st, A, lda, m, C, Bin, ldi, Bout, ldo,
-                       nb, D, mode, part);
-  else
-    hipLaunchKernelGGL((update_kernel<TA, TI, 4>), dim3(G), dim3(256), shm, st, A, lda, m, C, Bin, ldi, Bout, ldo,
-                       nb, D, mode, part);
+  const int mi = (mt + waves - 1) / waves;
+#define UPD_LAUNCH(W, MI, MC)                                                                                     \
+  hipLaunchKernelGGL((update_kernel<TA, TI, W, MI, MC>), dim3(G), dim3(W * 64), shm, st, A, lda, m, C, Bin, ldi, \
+                     Bout, ldo, nb, D, mode, part)
+  if (waves == 8) {
+    if (ct == 1) {
+      if (mi <= 2) UPD_LAUNCH(8, 2, 1);
+      else if (mi <= 4) UPD_LAUNCH(8, 4, 1);
+      else UPD_LAUNCH(8, 6, 1);
+    } else if (ct == 2) {
+      if (mi <= 3) UPD_LAUNCH(8, 3, 2);
+      else UPD_LAUNCH(8, 6, 2);
+    } else {
+      UPD_LAUNCH(8, 6, 4);
+    }
+  } else {
+    if (ct <= 2) UPD_LAUNCH(4, 12, 2);
+    else UPD_LAUNCH(4, 12, 4);
+  }
+#undef UPD_LAUNCH
   if (mode) {
     if (Pout)
       hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((plen + 255) / 256)), dim3(256), 0, st, part, G,

@@ -3,9 +3,9 @@
 //
 //   1. Householder reduction to tridiagonal form (A = Q Tri Q^T), reflectors kept;
 //   2. eigenvalues by Sturm-sequence bisection (one thread per wanted index);
-//   3. eigenvectors of Tri by inverse iteration with a pivoted LU of (Tri - lambda I);
-//      eigenvalues closer than 1e-3 ||T|| form a cluster whose vectors are
-//      orthogonalised against the earlier members at every iteration;
+//   3. eigenvectors of Tri by inverse iteration with a pivoted LU of (Tri - lambda I),
+//      one thread per vector, then Cholesky QR (twice) of the vector block so that
+//      vectors of close eigenvalues are orthonormal;
 //   4. back-transformation U = Q Z.
 // Textbook methods (Householder; Sturm-sequence bisection; inverse iteration),
 // written for this library.
@@ -56,8 +56,6 @@ __global__ __launch_bounds__(EIG_THREADS) void symeig_kernel(const double* __res
                                                              int ldu, double* __restrict__ A, double* __restrict__ Z,
                                                              double* __restrict__ LU) {
   __shared__ double d[EIG_NMAX], e[EIG_NMAX], e2[EIG_NMAX], vv[EIG_NMAX], pw[EIG_NMAX], lam[EIG_NMAX];
-  __shared__ int cstart[EIG_NMAX + 1];
-  __shared__ int ncl;
   __shared__ double red[32], wlo[16], whi[16], wnm[16];
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6, nwave = nthr >> 6;
@@ -165,98 +163,129 @@ __global__ __launch_bounds__(EIG_THREADS) void symeig_kernel(const double* __res
   }
   __syncthreads();
 
-  // ---- 3. clusters of close eigenvalues among the nvec lowest
-  if (tid == 0) {
-    const double gap = 1e-3 * tnorm;
-    int c = 0;
-    cstart[0] = 0;
-    for (int j = 1; j < nvec; j++)
-      if (lam[j] - lam[j - 1] > gap) cstart[++c] = j;
-    ncl = c + 1;
-    cstart[ncl] = nvec;
-  }
-  __syncthreads();
-  // inverse iteration: thread c handles cluster c sequentially.
+  // ---- 3. inverse iteration, one thread per wanted vector. The pivoted LU of (Tri - lambda I)
+  // is computed with the running pivot row kept in registers and written out once; the
+  // solves stream through it. Vectors are orthonormalised afterwards (Cholesky QR).
   // LU layout: array q, entry i of vector j at LU[(q * n + i) * nvec + j] (coalesced over j).
-  for (int c = tid; c < ncl; c += nthr) {
-    for (int j = cstart[c]; j < cstart[c + 1]; j++) {
-      double* dl = LU + (0 * (int64_t)n) * nvec + j;
-      double* dd = LU + (1 * (int64_t)n) * nvec + j;
-      double* du = LU + (2 * (int64_t)n) * nvec + j;
-      double* du2 = LU + (3 * (int64_t)n) * nvec + j;
-      double* pv = LU + (4 * (int64_t)n) * nvec + j;
+  for (int j = tid; j < nvec; j += nthr) {
+    double* dl = LU + (0 * (int64_t)n) * nvec + j;
+    double* dd = LU + (1 * (int64_t)n) * nvec + j;
+    double* du = LU + (2 * (int64_t)n) * nvec + j;
+    double* du2 = LU + (3 * (int64_t)n) * nvec + j;
+    double* pv = LU + (4 * (int64_t)n) * nvec + j;
 #define AT(p, i) (p)[(int64_t)(i) * nvec]
-      const double lm = lam[j];
-      for (int i = 0; i < n; i++) {
-        AT(dd, i) = d[i] - lm;
-        AT(du, i) = e[i];
-        AT(dl, i) = e[i];
-        AT(du2, i) = 0.0;
-        AT(pv, i) = 0.0;
+    const double lm = lam[j];
+    const double tiny = DBL_EPSILON * tnorm;
+    // running values of the current pivot row: a = dd[i], u1 = du[i]
+    double a = d[0] - lm, u1 = e[0];
+    for (int i = 0; i + 1 < n; i++) {
+      const double b = e[i];                  // sub-diagonal below the pivot
+      const double dnext = d[i + 1] - lm, enext = (i + 2 < n) ? e[i + 1] : 0.0;
+      double piv, sup, sup2, mult, na, nu1;
+      bool sw;
+      if (fabs(a) >= fabs(b)) {
+        sw = false;
+        piv = a;
+        sup = u1;
+        sup2 = 0.0;
+        mult = (a != 0.0) ? b / a : 0.0;
+        na = dnext - mult * u1;
+        nu1 = enext;
+      } else {
+        sw = true;
+        piv = b;
+        sup = dnext;
+        sup2 = enext;
+        mult = a / b;
+        na = u1 - mult * dnext;
+        nu1 = -mult * enext;
       }
-      // pivoted LU of the tridiagonal (Tri - lambda I)
-      for (int i = 0; i + 1 < n; i++) {
-        const double a = AT(dd, i), b = AT(dl, i);
-        if (fabs(a) >= fabs(b)) {
-          const double f = (a != 0.0) ? b / a : 0.0;
-          AT(dl, i) = f;
-          AT(dd, i + 1) -= f * AT(du, i);
-          AT(du2, i) = 0.0;
-        } else {
-          const double f = a / b;
-          AT(dd, i) = b;
-          AT(dl, i) = f;
-          const double t = AT(du, i);
-          AT(du, i) = AT(dd, i + 1);
-          AT(dd, i + 1) = t - f * AT(dd, i + 1);
-          if (i + 2 < n) {
-            AT(du2, i) = AT(du, i + 1);
-            AT(du, i + 1) = -f * AT(du2, i);
-          } else {
-            AT(du2, i) = 0.0;
-          }
-          AT(pv, i) = 1.0;
-        }
-      }
-      const double tiny = DBL_EPSILON * tnorm;
-      for (int i = 0; i < n; i++)
-        if (fabs(AT(dd, i)) < tiny) AT(dd, i) = (AT(dd, i) < 0.0) ? -tiny : tiny;
-      double* z = Z + j;  // column j of Z, stride nvec
-      uint64_t h = mix64(0x5D0C5EEDull + (uint64_t)j * 1315423911ull);
-      for (int i = 0; i < n; i++) {
-        h = mix64(h + i);
-        AT(z, i) = ((double)(h >> 11) * (1.0 / 9007199254740992.0)) - 0.5;
-      }
-      for (int it = 0; it < 4; it++) {
-        for (int i = 0; i + 1 < n; i++) {  // forward: P and L
-          if (AT(pv, i) != 0.0) {
-            const double t = AT(z, i);
-            AT(z, i) = AT(z, i + 1);
-            AT(z, i + 1) = t;
-          }
-          AT(z, i + 1) -= AT(dl, i) * AT(z, i);
-        }
-        AT(z, n - 1) /= AT(dd, n - 1);  // backward: U
-        if (n >= 2) AT(z, n - 2) = (AT(z, n - 2) - AT(du, n - 2) * AT(z, n - 1)) / AT(dd, n - 2);
-        for (int i = n - 3; i >= 0; i--)
-          AT(z, i) = (AT(z, i) - AT(du, i) * AT(z, i + 1) - AT(du2, i) * AT(z, i + 2)) / AT(dd, i);
-        for (int pass = 0; pass < 2; pass++) {  // against earlier cluster members
-          for (int q = cstart[c]; q < j; q++) {
-            const double* y = Z + q;
-            double s = 0.0;
-            for (int i = 0; i < n; i++) s += AT(y, i) * AT(z, i);
-            for (int i = 0; i < n; i++) AT(z, i) -= s * AT(y, i);
-          }
-        }
-        double nr = 0.0;
-        for (int i = 0; i < n; i++) nr += AT(z, i) * AT(z, i);
-        nr = 1.0 / sqrt(nr);
-        for (int i = 0; i < n; i++) AT(z, i) *= nr;
-      }
-#undef AT
+      if (fabs(piv) < tiny) piv = (piv < 0.0) ? -tiny : tiny;
+      AT(dd, i) = piv;
+      AT(du, i) = sup;
+      AT(du2, i) = sup2;
+      AT(dl, i) = mult;
+      AT(pv, i) = sw ? 1.0 : 0.0;
+      a = na;
+      u1 = nu1;
     }
+    if (fabs(a) < tiny) a = (a < 0.0) ? -tiny : tiny;
+    AT(dd, n - 1) = a;
+    AT(du, n - 1) = 0.0;
+    AT(du2, n - 1) = 0.0;
+    double* z = Z + j;  // column j of Z, stride nvec
+    uint64_t h = mix64(0x5D0C5EEDull + (uint64_t)j * 1315423911ull);
+    for (int i = 0; i < n; i++) {
+      h = mix64(h + i);
+      AT(z, i) = ((double)(h >> 11) * (1.0 / 9007199254740992.0)) - 0.5;
+    }
+    for (int it = 0; it < 3; it++) {
+      // forward: row interchanges and L, with the two live entries in registers
+      double zc = AT(z, 0);
+      for (int i = 0; i + 1 < n; i++) {
+        double zn = AT(z, i + 1);
+        if (AT(pv, i) != 0.0) {
+          const double t = zc;
+          zc = zn;
+          zn = t;
+        }
+        AT(z, i) = zc;
+        zc = zn - AT(dl, i) * zc;
+      }
+      AT(z, n - 1) = zc;
+      // backward: U, carrying z[i+1], z[i+2]
+      double z1 = AT(z, n - 1) / AT(dd, n - 1), z2 = 0.0;
+      AT(z, n - 1) = z1;
+      for (int i = n - 2; i >= 0; i--) {
+        const double zi = (AT(z, i) - AT(du, i) * z1 - AT(du2, i) * z2) / AT(dd, i);
+        AT(z, i) = zi;
+        z2 = z1;
+        z1 = zi;
+      }
+      double nr = 0.0;
+      for (int i = 0; i < n; i++) nr += AT(z, i) * AT(z, i);
+      nr = 1.0 / sqrt(nr);
+      for (int i = 0; i < n; i++) AT(z, i) *= nr;
+    }
+#undef AT
   }
   __syncthreads();
+  // Cholesky QR, twice, of Z (n x nvec): G = Z^T Z in A's space (A rows are still needed:
+  // the reflectors live in the upper part, so use LU's storage for G and R).
+  double* G = LU;  // nvec x nvec
+  for (int pass = 0; pass < 2 && nvec > 1; pass++) {
+    for (int64_t q = tid; q < (int64_t)nvec * nvec; q += nthr) {
+      const int r = (int)(q / nvec), c = (int)(q % nvec);
+      if (c < r) continue;
+      double s = 0.0;
+      for (int i = 0; i < n; i++) s += Z[(int64_t)i * nvec + r] * Z[(int64_t)i * nvec + c];
+      G[(int64_t)r * nvec + c] = s;
+    }
+    __syncthreads();
+    // upper Cholesky G = R^T R in place (row k finalised at step k)
+    for (int k = 0; k < nvec; k++) {
+      if (tid == 0) G[(int64_t)k * nvec + k] = sqrt(fmax(G[(int64_t)k * nvec + k], 1e-300));
+      __syncthreads();
+      const double rkk = G[(int64_t)k * nvec + k];
+      for (int c = k + 1 + tid; c < nvec; c += nthr) G[(int64_t)k * nvec + c] /= rkk;
+      __syncthreads();
+      for (int64_t q = tid; q < (int64_t)(nvec - k - 1) * (nvec - k - 1); q += nthr) {
+        const int r = k + 1 + (int)(q / (nvec - k - 1)), c = k + 1 + (int)(q % (nvec - k - 1));
+        if (c >= r) G[(int64_t)r * nvec + c] -= G[(int64_t)k * nvec + r] * G[(int64_t)k * nvec + c];
+      }
+      __syncthreads();
+    }
+    // Z <- Z R^-1: each row of Z solves x R = z (forward over columns)
+    for (int i = tid; i < n; i += nthr) {
+      double* zr = Z + (int64_t)i * nvec;
+      for (int c = 0; c < nvec; c++) {
+        double s = zr[c];
+        for (int r = 0; r < c; r++) s -= zr[r] * G[(int64_t)r * nvec + c];
+        zr[c] = s / G[(int64_t)c * nvec + c];
+      }
+    }
+    __syncthreads();
+  }
 
   // ---- 4. back-transformation U = H_0 H_1 ... H_{n-3} Z (apply reflectors last to first)
   for (int k = n - 3; k >= 0; k--) {
@@ -280,7 +309,7 @@ void symeig(const double* T, int ldt, int n, int nvec, double* theta, double* U,
   (void)orth;
   w.a.alloc((size_t)n * n * sizeof(double));
   w.z.alloc((size_t)n * nvec * sizeof(double));
-  w.lu.alloc((size_t)5 * n * nvec * sizeof(double));
+  w.lu.alloc((size_t)std::max(5 * n * nvec, nvec * nvec) * sizeof(double));
   hipLaunchKernelGGL(symeig_kernel, dim3(1), dim3(EIG_THREADS), 0, st, T, ldt, n, nvec, theta, U, ldu, w.a.as<double>(),
                      w.z.as<double>(), w.lu.as<double>());
   TRBL_HIP(hipGetLastError());

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <memory>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -101,13 +102,23 @@ struct DeviceTables {
   DevBuf pwords, nwords, ppart, npart, psec_start, psec_size, nsec_start, nsec_size, blk_of_sec;
   DevBuf psec_tm, psec_par, nsec_tm, nsec_par;
   // jumps
-  DevBuf pj_start, pj_idx, pj_meta, nj_start, nj_idx, nj_meta;
+  DevBuf pj_start, pj_idx, pj_meta, nj_start, nj_idx, nj_meta, pj_pack, nj_pack;  // nj_* class-major
   DevBuf h_off, h_ncol, h64, h32;
   DevBuf pp_ptr, pp_col, pp_v64, pp_v32, nn_ptr, nn_col, nn_v64, nn_v32;
+  DevBuf pe_off, pe_w, pe_col, pe_v64, pe_v32, ne_off, ne_w, ne_col, ne_v64, ne_v32;  // sliced ELL
+  DevBuf blk_pslice0, blk_nslice0;  // first ELL slice of each block's proton / neutron sector
   // gradient bins: per identical-particle operator entry / pn op pair, which m-scheme term
   DevBuf pp_term, nn_term;  // per CSR entry: list range into term lists
   DevBuf pp_tptr, pp_tid, pp_tsgn, nn_tptr, nn_tid, nn_tsgn;
   DevBuf h_term;            // per pn table entry: m-scheme pn term id (-1 if none)
+};
+
+// Work decomposition of one block H.V launch (hv.hip), owned by the model.
+struct HVPlan {
+  int C = 1, ntile = 1, nchunk_r = 1, nchunk_c = 1, maxp_r = 1, maxp_c = 1, nthr_r = 64, nthr_c = 64;
+  int64_t rows_items = 0, cols_items = 0;
+  size_t shm_r = 0, shm_c = 0, row_bytes = 0, ent_bytes = 0, hs_bytes = 0;
+  DevBuf item0, citem0;
 };
 
 struct MTerm {  // m-scheme two-body term c+_a c+_b c_d c_c (species-local state indices)
@@ -126,6 +137,7 @@ struct Model {
   int64_t dim = 0;
   Classes cl;
   int device = 0;
+  mutable std::unordered_map<int, std::unique_ptr<HVPlan>> hv_plans;  // key: nb * 16 + sizeof(T)
   // Hamiltonian
   bool has_h = false;
   std::vector<double> spe[2];
@@ -141,6 +153,7 @@ struct Model {
   int max_dn = 0, max_dp = 0;
   std::vector<int> h_off_host, h_ncol_host;
   std::vector<int64_t> blk_item0_host;  // prefix of rows per block (for row kernels)
+  std::vector<int> sec_slice0[2];       // per species sector: first sliced-ELL slice
 };
 
 // host helpers (model.cpp)

@@ -420,6 +420,39 @@ void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const
       ptr.push_back((int)col.size());
     }
     std::vector<float> val32(val.begin(), val.end());
+    // sliced-ELL copy for the H.V kernels: slices of 64 consecutive SDs of one sector (one
+    // wavefront of targets), padded to the longest row of the slice, entry k of lane l at
+    // base + k * 64 + l so the 64 lanes of a wavefront read 64 consecutive entries.
+    {
+      std::vector<int> soff, sw, sec_slice0, ecol;
+      std::vector<double> eval;
+      for (const auto& sec : S.sectors) {
+        sec_slice0.push_back((int)sw.size());
+        for (int r0 = 0; r0 < sec.size; r0 += 64) {
+          int w = 0;
+          for (int r = r0; r < std::min(sec.size, r0 + 64); r++)
+            w = std::max(w, ptr[sec.start + r + 1] - ptr[sec.start + r]);
+          soff.push_back((int)ecol.size());
+          sw.push_back(w);
+          const size_t base = ecol.size();
+          ecol.resize(base + (size_t)w * 64, 0);
+          eval.resize(base + (size_t)w * 64, 0.0);
+          for (int r = r0; r < std::min(sec.size, r0 + 64); r++)
+            for (int k = ptr[sec.start + r]; k < ptr[sec.start + r + 1]; k++) {
+              const size_t at = base + (size_t)(k - ptr[sec.start + r]) * 64 + (r - r0);
+              ecol[at] = col[k];
+              eval[at] = val[k];
+            }
+        }
+      }
+      std::vector<float> eval32(eval.begin(), eval.end());
+      (s == 0 ? m.dt.pe_off : m.dt.ne_off).upload(soff);
+      (s == 0 ? m.dt.pe_w : m.dt.ne_w).upload(sw);
+      (s == 0 ? m.dt.pe_col : m.dt.ne_col).upload(ecol);
+      (s == 0 ? m.dt.pe_v64 : m.dt.ne_v64).upload(eval);
+      (s == 0 ? m.dt.pe_v32 : m.dt.ne_v32).upload(eval32);
+      m.sec_slice0[s] = sec_slice0;
+    }
     (s == 0 ? m.dt.pp_ptr : m.dt.nn_ptr).upload(ptr);
     (s == 0 ? m.dt.pp_col : m.dt.nn_col).upload(col);
     (s == 0 ? m.dt.pp_v64 : m.dt.nn_v64).upload(val);
@@ -427,6 +460,16 @@ void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const
     (s == 0 ? m.dt.pp_tptr : m.dt.nn_tptr).upload(tptr);
     (s == 0 ? m.dt.pp_tid : m.dt.nn_tid).upload(tid);
     (s == 0 ? m.dt.pp_tsgn : m.dt.nn_tsgn).upload(tsg);
+  }
+
+  {
+    std::vector<int> ps0, ns0;
+    for (const auto& b : m.blocks) {
+      ps0.push_back(m.sec_slice0[0][b.psec]);
+      ns0.push_back(m.sec_slice0[1][b.nsec]);
+    }
+    m.dt.blk_pslice0.upload(ps0);
+    m.dt.blk_nslice0.upload(ns0);
   }
 
   // ---------------- one-body jumps and the pn coefficient table (App. B, second part)
@@ -473,17 +516,17 @@ void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const
   m.dt.h64.upload(h);
   m.dt.h32.upload(h32);
   m.dt.h_term.upload(hterm);
-  // jump lists: from each SD g' remove x in g', add y not in g' \ {x} (y == x allowed)
+  // jump lists: from each SD g' remove x in g', add y not in g' \ {x} (y == x allowed).
+  // Proton side: per (SD, class), sorted by source index so equal source rows are adjacent.
+  // Neutron side: class-major, so the lists of consecutive SDs in one class are contiguous.
   for (int s = 0; s < 2; s++) {
     const Species& S = m.sp[s];
     const std::vector<int>& oidx = s == 0 ? pop_idx : nop_idx;
     const std::vector<int>& ocls = s == 0 ? pop_cls : nop_cls;
     const int64_t nsd = (int64_t)S.words.size();
-    std::vector<int> start(nsd * ncl + 1, 0);
-    std::vector<int> jidx, jmeta;
-    std::vector<std::vector<std::pair<int, int>>> bucket(ncl);
+    std::vector<std::vector<std::vector<std::pair<int, int>>>> all(nsd, std::vector<std::vector<std::pair<int, int>>>(ncl));
     for (int64_t g = 0; g < nsd; g++) {
-      for (auto& bk : bucket) bk.clear();
+      auto& bucket = all[g];
       uint64_t w = S.words[g];
       for (uint64_t xx = w; xx; xx &= xx - 1) {
         int x = __builtin_ctzll(xx);
@@ -499,18 +542,42 @@ void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const
           bucket[c].push_back({local, (oidx[x * ns + y] << 1) | (sy < 0 ? 1 : 0)});
         }
       }
-      for (int c = 0; c < ncl; c++) {
-        start[g * ncl + c] = (int)jidx.size();
-        for (auto& pr : bucket[c]) {
-          jidx.push_back(pr.first);
-          jmeta.push_back(pr.second);
+      for (auto& b : bucket) std::stable_sort(b.begin(), b.end(), [](auto& u, auto& v) { return u.first < v.first; });
+    }
+    std::vector<int> start, jidx, jmeta;
+    if (s == 0) {
+      start.assign(nsd * ncl + 1, 0);
+      for (int64_t g = 0; g < nsd; g++)
+        for (int c = 0; c < ncl; c++) {
+          start[g * ncl + c] = (int)jidx.size();
+          for (auto& pr : all[g][c]) {
+            jidx.push_back(pr.first);
+            jmeta.push_back(pr.second);
+          }
         }
+      start[nsd * ncl] = (int)jidx.size();
+    } else {
+      start.assign((int64_t)ncl * (nsd + 1), 0);
+      for (int c = 0; c < ncl; c++) {
+        for (int64_t g = 0; g < nsd; g++) {
+          start[c * (nsd + 1) + g] = (int)jidx.size();
+          for (auto& pr : all[g][c]) {
+            jidx.push_back(pr.first);
+            jmeta.push_back(pr.second);
+          }
+        }
+        start[c * (nsd + 1) + nsd] = (int)jidx.size();
       }
     }
-    start[nsd * ncl] = (int)jidx.size();
+    std::vector<int> pack(2 * jidx.size());
+    for (size_t q = 0; q < jidx.size(); q++) {
+      pack[2 * q] = jidx[q];
+      pack[2 * q + 1] = jmeta[q];
+    }
     (s == 0 ? m.dt.pj_start : m.dt.nj_start).upload(start);
     (s == 0 ? m.dt.pj_idx : m.dt.nj_idx).upload(jidx);
     (s == 0 ? m.dt.pj_meta : m.dt.nj_meta).upload(jmeta);
+    (s == 0 ? m.dt.pj_pack : m.dt.nj_pack).upload(pack);
     (s == 0 ? m.pj_count : m.nj_count) = (int)jidx.size();
   }
   m.has_h = true;

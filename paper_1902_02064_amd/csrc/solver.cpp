@@ -17,6 +17,8 @@
 // Rayleigh-Ritz step on the Ritz vectors refines the eigenvalues.
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 #include "dense.h"
 
@@ -57,6 +59,8 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
   hipStream_t st = (hipStream_t)o.stream;
   // an FP32 residual cannot fall far below the FP32 rounding of H.V: floor the tolerance
   const double tol = mixed ? std::max(o.tol, 1e-5) : o.tol;
+  const char* vb = std::getenv("TRBL_VERBOSE");
+  const bool verbose = vb && vb[0] && vb[0] != '0';
   const auto t_begin = std::chrono::steady_clock::now();
 
   const int64_t ldq = round4(lm);
@@ -143,8 +147,19 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
     apply_small<double, TQ>(W, nb, R2i, Q + mcur, ldq, nb, D, false, sc, st);
     t_beta(T, lm, c0, mcur, nb, beta, st);
     TRBL_HIP(hipEventRecord(ev.e[3], st));
-    // diagonalise T^(k)
+    // diagonalise T^(k) (every check_every iterations and before every restart)
     const bool restart_next = mcur + 2 * nb > lm;
+    const int every = std::max(1, o.check_every);
+    if (!restart_next && it % every != 0 && it < o.max_iter) {
+      TRBL_HIP(hipMemcpyAsync(sth, status, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+      TRBL_HIP(hipStreamSynchronize(st));
+      t_hv += ev.ms(0, 1);
+      t_orth += ev.ms(1, 2);
+      t_qr += ev.ms(2, 3);
+      TRBL_REQUIRE(sth[0] == 0 && sth[1] == 0, TRBL_E_BREAKDOWN,
+                   "block Lanczos breakdown: new block is numerically rank deficient");
+      continue;
+    }
     const int nvec = restart_next ? ls : std::min(neig, mcur);
     symeig(T, lm, mcur, nvec, theta, U, ldu, ew, restart_next, st);
     nchk = std::min(neig, mcur);
@@ -164,7 +179,17 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
                  "block Lanczos breakdown: new block is numerically rank deficient");
     hnorm = std::max(hnorm, std::max(std::fabs(th[0]), std::fabs(tmax)));
     bool ok = nchk == neig;
+    int nconv_it = 0;
+    for (int i = 0; i < nchk; i++) nconv_it += rh[i] <= tol * hnorm;
     for (int i = 0; ok && i < nchk; i++) ok = rh[i] <= tol * hnorm;
+    if (verbose) {
+      double rmax = 0.0;
+      for (int i = 0; i < nchk; i++) rmax = std::max(rmax, rh[i]);
+      std::fprintf(stderr, "trbl it %d m %d conv %d/%d rmax %.3e th0 %.10f | hv %.2f orth %.2f qr %.2f eig %.2f ms\n",
+                   it, mcur, nconv_it, neig, rmax / std::max(hnorm, 1e-300), th[0], ev.ms(0, 1) * 1e3,
+                   ev.ms(1, 2) * 1e3, ev.ms(2, 3) * 1e3, ev.ms(3, 4) * 1e3);
+      std::fflush(stderr);
+    }
     if (ok) {
       converged = true;
       break;
