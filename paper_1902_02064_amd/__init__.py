@@ -61,6 +61,8 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} not built; run paper_1902_02064_amd/build.py")
+    # torch first: the library must bind to the HIP runtime that owns torch's device memory and streams
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P, I, I64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
     sig = {

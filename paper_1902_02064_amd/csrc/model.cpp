@@ -304,19 +304,18 @@ void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const
     TRBL_REQUIRE(((m.orbits[e.a].l + m.orbits[e.b].l + m.orbits[e.c].l + m.orbits[e.d].l) & 1) == 0,
                  TRBL_E_INVALID, "element breaks parity");
     const bool ident = e.channel != 2;
+    double ph = 1.0;  // reordering phase: the canonical element is ph * v
     if (ident) {
       TRBL_REQUIRE(!(e.a == e.b && ((e.twoJ / 2) & 1)) && !(e.c == e.d && ((e.twoJ / 2) & 1)), TRBL_E_INVALID,
                    "identical nucleons in one j-shell couple to even J only");
-      double val = e.v;
       if (e.a > e.b) {
         std::swap(e.a, e.b);
-        val *= -((((twoj(e.a) + twoj(e.b) - e.twoJ) / 2) & 1) ? -1.0 : 1.0);
+        ph *= -((((twoj(e.a) + twoj(e.b) - e.twoJ) / 2) & 1) ? -1.0 : 1.0);
       }
       if (e.c > e.d) {
         std::swap(e.c, e.d);
-        val *= -((((twoj(e.c) + twoj(e.d) - e.twoJ) / 2) & 1) ? -1.0 : 1.0);
+        ph *= -((((twoj(e.c) + twoj(e.d) - e.twoJ) / 2) & 1) ? -1.0 : 1.0);
       }
-      e.v = val;
     }
     // the pair of pair-states and its mirror
     int prs[2][4] = {{e.a, e.b, e.c, e.d}, {e.c, e.d, e.a, e.b}};
@@ -341,7 +340,7 @@ void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const
               if (m.st_tm[s3] + m.st_tm[s4] != tM) continue;
               double c2 = clebsch(twoj(C), m.st_tm[s3], twoj(D), m.st_tm[s4], e.twoJ, tM);
               if (c2 == 0.0) continue;
-              acc[e.channel].add(s1, s2, s3, s4, nab * ncd * c1 * c2, e.v, (int)t);
+              acc[e.channel].add(s1, s2, s3, s4, ph * nab * ncd * c1 * c2, e.v, (int)t);
             }
           }
         }

@@ -1,0 +1,135 @@
+"""Gradient of a weighted eigenvalue sum (trbl_tbme_grad) against the oracle and finite differences (GPU)."""
+import os
+
+import numpy as np
+import pytest
+
+from gpu_common import pair, say
+from oracle.grad import spe_gradient, tbme_gradient
+from workloads import SD_ORBITS, WORKLOADS, grad_weights, random_tbme
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _oracle_grad(o, tbme, n, w):
+    e, U = np.linalg.eigh(o.dense())
+    X = U[:, :n]
+    return tbme_gradient(o, tbme, X, w), spe_gradient(o, X, w), e[:n]
+
+
+@pytest.fixture(scope="module")
+def sd22():
+    w = WORKLOADS["sd22"]
+    tb = w.tbme()
+    g, o = pair(w.orbits, w.n_prot, w.n_neut, w.twoM, tb, w.spe, w.spe)
+    return w, tb, g, o
+
+
+def test_grad_matches_oracle_sd22(sd22):
+    """Densities from GPU eigenvectors contracted on the device side vs the oracle's unit-Hamiltonian sums."""
+    w, tb, g, o = sd22
+    n = w.n_eig
+    wt = grad_weights(n)
+    say("grad sd22 (eigenvectors recomputed by the library)")
+    gv, gs = g.tbme_grad(wt, nb=w.nb, tol=1e-11)
+    ov, os_, _ = _oracle_grad(o, tb, n, wt)
+    scale = np.abs(ov).max()
+    say("max abs diff V", np.abs(gv - ov).max(), "spe", np.abs(gs - os_).max(), "scale", scale)
+    assert np.abs(gv - ov).max() <= 1e-8 * scale
+    assert np.abs(gs - os_).max() <= 1e-8 * np.abs(os_).max()
+
+
+def test_grad_given_evecs_and_euler(sd22):
+    """Passing eigenvectors; Euler: H is linear and homogeneous in (e, V), so sum v g_v + sum e g_e = sum w E."""
+    w, tb, g, o = sd22
+    n = 6
+    wt = grad_weights(n, 3)
+    ev, X, info = g.solve(w.nb, n, 2 * n, 40, 1e-11, "fp64", vectors=True)
+    gv, gs = g.tbme_grad(wt, evecs=X)
+    vals = np.array([t[6] for t in tb])
+    euler = vals @ gv + np.concatenate([w.spe, w.spe]) @ gs
+    say("euler", euler, "sum wE", wt @ ev)
+    assert abs(euler - wt @ ev) <= 1e-10 * np.abs(ev).max() * wt.sum()
+
+
+def test_grad_reordered_pairs_and_mixed_parity():
+    """Identical-particle pairs listed as (b,a) carry the exchange phase into the gradient; both parities."""
+    orbits = SD_ORBITS
+    tb = random_tbme(orbits, 5, 1.0)
+    tw = [o[2] for o in orbits]
+    out = []
+    for k, t in enumerate(tb):
+        ch, a, b, c, d, J2, v = t
+        if ch != 2 and a != b and k % 3 == 0:
+            ph = -(-1) ** ((tw[a] + tw[b] - J2) // 2)
+            out.append((ch, b, a, c, d, J2, ph * v))
+        else:
+            out.append(t)
+    spe = (-1.1, 0.4, 2.0)
+    g, o = pair(orbits, 2, 3, 1, out, spe, spe, parity=0)
+    n = 5
+    wt = grad_weights(n, 11)
+    gv, gs = g.tbme_grad(wt, nb=4, tol=1e-11)
+    ov, os_, _ = _oracle_grad(o, out, n, wt)
+    say("reordered: max abs diff", np.abs(gv - ov).max())
+    assert np.abs(gv - ov).max() <= 1e-8 * np.abs(ov).max()
+    assert np.abs(gs - os_).max() <= 1e-8 * np.abs(os_).max()
+
+
+def test_grad_finite_differences(sd22):
+    """Central differences (h = 1e-5) of sum w_k E_k from GPU solves, for several elements and energies."""
+    w, tb, g, o = sd22
+    n = 8
+    wt = grad_weights(n, 5)
+    gv, gs = g.tbme_grad(wt, nb=w.nb, tol=1e-12)
+    h = 1e-5
+
+    def f(tbl, sp_p, sp_n):
+        g.set_hamiltonian(sp_p, sp_n, tbl)
+        ev, _, info = g.solve(w.nb, n, 2 * n, 48, 1e-12, "fp64")
+        assert info.converged
+        return wt @ ev
+
+    picks = [0, 7, 31, 64, 100, len(tb) - 1]
+    spe = list(w.spe)
+    for t in picks:
+        up = list(tb)
+        dn = list(tb)
+        up[t] = tb[t][:6] + (tb[t][6] + h,)
+        dn[t] = tb[t][:6] + (tb[t][6] - h,)
+        fd = (f(up, spe, spe) - f(dn, spe, spe)) / (2 * h)
+        say("element", t, tb[t][:6], "fd", fd, "grad", gv[t])
+        assert abs(fd - gv[t]) <= 1e-5 * max(1.0, abs(gv[t]))
+    for q in (0, 4):
+        sp = [list(spe), list(spe)]
+        sm = [list(spe), list(spe)]
+        sp[q // 3][q % 3] += h
+        sm[q // 3][q % 3] -= h
+        fd = (f(tb, *sp) - f(tb, *sm)) / (2 * h)
+        say("spe", q, "fd", fd, "grad", gs[q])
+        assert abs(fd - gs[q]) <= 1e-5 * max(1.0, abs(gs[q]))
+    g.set_hamiltonian(w.spe, w.spe, tb)
+
+
+def test_grad_sd66_full_size_golden():
+    """sd shell 6+6 (D = 93,710), 20 lowest, weights grad_weights(20, 7): stored oracle gradient."""
+    path = os.path.join(GOLDEN, "sd66_grad.txt")
+    if not os.path.exists(path):
+        pytest.skip("sd66_grad.txt not generated")
+    ref = np.array([float(x) for x in open(path) if x.strip() and not x.startswith("#")])
+    w = WORKLOADS["sd66"]
+    tb = w.tbme()
+    g, _ = pair(w.orbits, w.n_prot, w.n_neut, w.twoM, tb, w.spe, w.spe, oracle=False)
+    wt = grad_weights(w.n_eig, w.extra["grad_weight_seed"])
+    say("solve + grad sd66")
+    ev, X, info = g.solve(w.nb, w.n_eig, w.l_s, w.l_m, w.tol, "fp64", vectors=True)
+    assert info.converged
+    gv, gs = g.tbme_grad(wt, evecs=X)
+    got = np.concatenate([gv, gs])
+    assert got.shape == ref.shape
+    err = np.abs(got - ref).max()
+    say("sd66 grad max abs diff", err, "scale", np.abs(ref).max())
+    assert err <= 1e-7 * np.abs(ref).max()
