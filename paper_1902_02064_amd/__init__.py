@@ -235,13 +235,17 @@ class Model:
         return np.array(ev[:]), X, si
 
     def tbme_grad(self, weights, evecs=None, nb=8, l_s=None, l_m=None, tol=1e-10, max_iter=5000, seed=1000,
-                  spe=True):
-        """d(sum_k w_k E_k)/dV for every element given to set_hamiltonian (and the spe if asked)."""
+                  spe=True, n_solve=None):
+        """d(sum_k w_k E_k)/dV for every element given to set_hamiltonian (and the spe if asked).
+
+        evecs: device [D][len(weights)] FP64 eigenvectors, or None to recompute them with a TRBL
+        solve for n_solve (default len(weights)) eigenpairs."""
         w = np.ascontiguousarray(weights, dtype=np.float64)
         n = len(w)
-        l_s = l_s or max(2 * n, n + nb)
+        ns = n_solve or n
+        l_s = l_s or max(2 * ns, ns + nb)
         l_m = l_m or min(self.dim, l_s + 6 * nb)
-        o = self._opts(nb, n, l_s, l_m, tol, "fp64", max_iter, seed, None, True)
+        o = self._opts(nb, ns, l_s, l_m, tol, "fp64", max_iter, seed, None, True)
         gv = np.zeros(max(1, self.n_tbme))
         gs = np.zeros(2 * len(self.orbits)) if spe else None
         _check(load().trbl_tbme_grad(self._h, ctypes.byref(o), n, w.ctypes.data_as(ctypes.c_void_p),
@@ -249,3 +253,46 @@ class Model:
                                      gv.ctypes.data_as(ctypes.c_void_p),
                                      None if gs is None else gs.ctypes.data_as(ctypes.c_void_p)))
         return gv[:self.n_tbme], gs
+
+
+def _autograd_fn():
+    import torch
+
+    class _Eigenvalues(torch.autograd.Function):
+        """E(V, e): lowest eigenvalues as a differentiable function of the J-coupled elements and the
+        single-particle energies. The backward pass is the Hellmann-Feynman density kernel of
+        trbl_tbme_grad: dL/dtheta = sum_k (dL/dE_k) <psi_k| dH/dtheta |psi_k>."""
+
+        @staticmethod
+        def forward(ctx, v, spe_p, spe_n, model, structure, solver, keep_vectors):
+            tb = [tuple(s) + (float(x),) for s, x in zip(structure, v.detach().cpu().tolist())]
+            model.set_hamiltonian(spe_p.detach().cpu().tolist(), spe_n.detach().cpu().tolist(), tb)
+            ev, X, info = model.solve(vectors=keep_vectors, **solver)
+            if not info.converged:
+                raise TrblError(TRBL_NOT_CONVERGED, "TRBL did not converge in forward")
+            ctx.model, ctx.solver, ctx.X = model, solver, X
+            ctx.norb = len(model.orbits)
+            return torch.from_numpy(ev).to(v.dtype)
+
+        @staticmethod
+        def backward(ctx, gE):
+            w = gE.detach().cpu().numpy().astype(np.float64)
+            s = ctx.solver
+            gv, gs = ctx.model.tbme_grad(w, evecs=ctx.X, nb=s["nb"], l_s=s.get("l_s"), l_m=s.get("l_m"),
+                                         tol=s["tol"], max_iter=s.get("max_iter", 5000), seed=s.get("seed", 1000),
+                                         n_solve=s["n_eig"])
+            gv = torch.from_numpy(gv).to(gE.dtype)
+            gp = torch.from_numpy(gs[:ctx.norb].copy()).to(gE.dtype)
+            gn = torch.from_numpy(gs[ctx.norb:].copy()).to(gE.dtype)
+            return gv, gp, gn, None, None, None, None
+
+    return _Eigenvalues
+
+
+def eigenvalues(model, structure, v, spe_p, spe_n, nb, n_eig, l_s, l_m, tol, max_iter=5000, seed=1000,
+                keep_vectors=True):
+    """Differentiable lowest eigenvalues (torch autograd). structure: (channel, a, b, c, d, 2J) per element;
+    v, spe_p, spe_n: CPU float64 tensors. keep_vectors=False recomputes the eigenvectors in the backward
+    pass instead of holding D x n_eig doubles on the device between the passes."""
+    solver = dict(nb=nb, n_eig=n_eig, l_s=l_s, l_m=l_m, tol=tol, max_iter=max_iter, seed=seed)
+    return _autograd_fn().apply(v, spe_p, spe_n, model, [tuple(s[:6]) for s in structure], solver, keep_vectors)

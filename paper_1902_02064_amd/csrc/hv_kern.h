@@ -1,0 +1,469 @@
+// On-the-fly block H.V (App. B) and device-side basis indexing (App. A).
+//
+// W = H V for nb vectors stored row-major [D][ld]. Every output row
+// (p', n') of a proton-major block b' is produced by one lane:
+//   identical-particle part  sum_p  Hpp[p',p] V[p, n']   (same block)
+//                          + sum_n  Hnn[n',n] V[p', n]   (same block)
+//   proton-neutron part      sum over proton jumps p' -> p (remove a, add c)
+//                            and neutron jumps n' -> n (remove b, add d) with
+//                            opposite change of M and the same parity flip:
+//                            s_p s_n h(a b c d) V[p, n]   (source block b)
+// (the factorisation c+_a c+_b c_d c_c = (c+_a c_c)_p (c+_b c_d)_n of App. B,
+// with Jordan-Wigner signs counted inside each species). Jumps include the
+// number operators (a == c), so the pn diagonal needs no special case. The
+// element h is generated from the class tables for every (p', n') and reused
+// across the C vectors of a column tile held in the lane's registers.
+//
+// The rows kernel owns one target proton row p' (one workgroup, one lane per
+// target neutron n'). The source rows V[p, :, tile] of its proton jumps are
+// streamed through two LDS buffers: while the lanes gather from one buffer,
+// the next source row is copied into the other by the global->LDS DMA of
+// gfx950 (no registers involved). Rows are stored plainly; a lane reads the
+// 16-byte chunks of a row starting at chunk (lane mod chunks-per-row), so the
+// lanes of a wavefront that gather from random rows still hit different LDS
+// banks at each step. Accumulator slot t of lane l therefore holds column chunk
+// (t + l) mod chunks-per-row, which the final store undoes.
+#pragma once
+#include "internal.h"
+
+namespace trbl {
+
+template <class T>
+struct HVArgs {
+  const T* V;
+  T* W;
+  int64_t ldv, ldw;
+  int nb, ncl, tjmax, nblocks;
+  int C, ntile, nchunk;  // column tile width, column tiles, target chunks per row/column
+  int dma;               // source rows copied by global->LDS DMA (16-byte aligned rows)
+  int64_t nn_total;
+  const int* blk_dp;
+  const int* blk_dn;
+  const int64_t* blk_off;
+  const int* blk_p0;
+  const int* blk_n0;
+  const int* src_blk;
+  const int* pj_start;
+  const int* pj_idx;
+  const int* pj_meta;
+  const int* nj_start;  // class-major: [cls * (nn_total + 1) + g]
+  const int2* nj_pack;  // (source local index, op << 1 | sign)
+  const int* h_off;
+  const int* h_ncol;
+  const T* h;
+  const int* pe_off;  // sliced-ELL identical-particle operators (proton, neutron)
+  const int* pe_w;
+  const int* pe_col;
+  const T* pe_val;
+  const int* ne_off;
+  const int* ne_w;
+  const int* ne_col;
+  const T* ne_val;
+  const int* blk_pslice0;
+  const int* blk_nslice0;
+  const int* bin_blocks;   // rows kernel: blocks of this launch
+  const int64_t* bin_item0;  // rows kernel: first work item of each of them (bin_nblk + 1)
+  int bin_nblk;
+  const int64_t* citem0;  // per block: first work item (columns kernel)
+};
+
+// Work item -> (block, row, column tile, target chunk); consecutive items go to one XCD.
+__device__ __forceinline__ int64_t xcd_item(int64_t bid, int64_t n) {
+  const int64_t per = (n + 7) / 8;
+  const int64_t x = bid % 8, q = bid / 8;
+  return x * per + q;
+}
+
+__device__ __forceinline__ int find_block(const int64_t* item0, int nblocks, int64_t item) {
+  int lo = 0, hi = nblocks - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (item0[mid] <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------- columns kernel helpers
+// padded LDS row stride (elements): > C and a multiple of 16 bytes so a row slice is 16-byte aligned
+template <class T, int C>
+constexpr int row_stride() {
+  return sizeof(T) == 8 ? (C >= 2 ? C + 2 : 2) : (C >= 4 ? C + 4 : 4);
+}
+
+// lds[r * RS + c] = src[r * rstride + c] for r < nrows, c < C (zero beyond cvalid)
+template <class T, int C>
+__device__ __forceinline__ void stage(T* lds, const T* src, int64_t rstride, int nrows, int cvalid) {
+  constexpr int RS = row_stride<T, C>();
+  const int n = nrows * C;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int r = e / C, c = e % C;
+    lds[r * RS + c] = (c < cvalid) ? src[(int64_t)r * rstride + c] : T(0);
+  }
+}
+
+template <class T, int C>
+__device__ __forceinline__ void axpy_row(T (&acc)[C], T coef, const T* x) {
+#pragma unroll
+  for (int c = 0; c < C; c++) acc[c] += coef * x[c];
+}
+
+// ---------------------------------------------------------------- rows kernel helpers
+// One row of a C-column tile in LDS: C * sizeof(T) bytes as CPR 16-byte chunks.
+template <class T, int C>
+struct Tile {
+  static constexpr int VPC = 16 / (int)sizeof(T);  // values per chunk
+  static constexpr int CPR = C / VPC;              // chunks per row
+  static constexpr int RB = C * (int)sizeof(T);    // bytes per row
+  static_assert(CPR >= 1 && (CPR & (CPR - 1)) == 0, "tile width must be a power-of-two number of chunks");
+  __device__ static __forceinline__ int at(int r, int k) { return r * RB + (k << 4); }
+  __device__ static __forceinline__ int rot() { return (int)threadIdx.x & (CPR - 1); }  // first chunk of this lane
+};
+
+// Asynchronous copy of nrows rows (C values each, row stride ld) into the tile. Each lane
+// moves one 16-byte chunk per instruction; the chunks of one wavefront land contiguously.
+template <class T, int C>
+__device__ __forceinline__ void stage_dma(char* lds, const T* src, int64_t ld, int nrows) {
+  using L = Tile<T, C>;
+  const int total = nrows * L::CPR;
+  const int lane = threadIdx.x & 63;
+  for (int s0 = threadIdx.x & ~63; s0 < total; s0 += blockDim.x) {
+    const int s = s0 + lane;
+    if (s < total) {
+      const int r = s / L::CPR, k = s % L::CPR;
+      __builtin_amdgcn_global_load_lds((const void*)(src + (int64_t)r * ld + k * L::VPC),
+                                       (__attribute__((address_space(3))) void*)(lds + (s0 << 4)), 16, 0, 0);
+    }
+  }
+}
+
+// Synchronous copy into the same layout (partial or unaligned column tiles), zero beyond cvalid.
+template <class T, int C>
+__device__ __forceinline__ void stage_sync(char* lds, const T* src, int64_t ld, int nrows, int cvalid) {
+  using L = Tile<T, C>;
+  const int total = nrows * L::CPR;
+  for (int s = threadIdx.x; s < total; s += blockDim.x) {
+    const int r = s / L::CPR, k = s % L::CPR;
+    T* d = reinterpret_cast<T*>(lds + L::at(r, k));
+#pragma unroll
+    for (int v = 0; v < L::VPC; v++) {
+      const int c = k * L::VPC + v;
+      d[v] = c < cvalid ? src[(int64_t)r * ld + c] : T(0);
+    }
+  }
+}
+
+// acc += coef * row r of the tile, accumulator slot t <- chunk (t + rot) mod CPR
+template <class T, int C>
+__device__ __forceinline__ void gather(T (&acc)[C], T coef, const char* lds, int r, int rot) {
+  using L = Tile<T, C>;
+  const char* row = lds + r * L::RB;
+#pragma unroll
+  for (int k = 0; k < L::CPR; k++) {
+    const char* p = row + (((k + rot) & (L::CPR - 1)) << 4);
+    if constexpr (sizeof(T) == 8) {
+      const double2 v = *reinterpret_cast<const double2*>(p);
+      acc[2 * k] += coef * v.x;
+      acc[2 * k + 1] += coef * v.y;
+    } else {
+      const float4 v = *reinterpret_cast<const float4*>(p);
+      acc[4 * k] += coef * v.x;
+      acc[4 * k + 1] += coef * v.y;
+      acc[4 * k + 2] += coef * v.z;
+      acc[4 * k + 3] += coef * v.w;
+    }
+  }
+}
+
+// Load of a workgroup-uniform table entry through the constant address space, so the
+// compiler issues a scalar load (counted apart from the vector loads and LDS DMA in flight).
+template <class U>
+__device__ __forceinline__ U ldu(const U* p, int64_t i) {
+  return ((const __attribute__((address_space(4))) U*)(p))[i];
+}
+
+// Proton jumps of one target SD are stored per class, sorted by source row; a group is a
+// run of jumps of one class with the same source row (several only for number operators).
+struct GroupIt {
+  int cls, jg, je, sb, p;
+};
+
+template <class T>
+__device__ __forceinline__ GroupIt next_group(const HVArgs<T>& a, int b, int gp, int cls, int j) {
+  const int ncl = a.ncl;
+  while (cls < ncl) {
+    const int j1 = ldu(a.pj_start, gp * ncl + cls + 1);
+    const int sb = ldu(a.src_blk, b * ncl + cls);
+    if (sb >= 0 && j < j1) {
+      const int p = ldu(a.pj_idx, j);
+      int je = j + 1;
+      while (je < j1 && ldu(a.pj_idx, je) == p) je++;
+      return {cls, j, je, sb, p};
+    }
+    cls++;
+    if (cls < ncl) j = ldu(a.pj_start, gp * ncl + cls);
+  }
+  return {ncl, 0, 0, -1, 0};
+}
+
+constexpr int MAXE = 8;           // neutron jumps per (target, class) kept in registers
+constexpr int HS_BYTES = 8192;    // LDS rows of the class table used by the target's proton jumps
+
+// Rows kernel: neutron-neutron and proton-neutron parts of W for one proton row p' of one
+// block (App. B). One lane owns target n' (sectors wider than 1024 are split in chunks) and the C
+// columns of the tile. Its neutron jumps of the current class sit in registers; the class
+// table rows of the proton ops sit in LDS; source rows stream through B0/B1.
+template <class T, int C, int NTB, int RBKB, bool DMA>
+__global__ __launch_bounds__(NTB) void hv_rows_kernel(HVArgs<T> a) {
+  constexpr int MAXP = 1;  // targets per lane (wider sectors are split into chunks)
+  constexpr int RBYTES = RBKB * 1024;
+  constexpr int HSN = HS_BYTES / (int)sizeof(T);
+  __shared__ __align__(16) char B0[RBYTES];
+  __shared__ __align__(16) char B1[RBYTES];
+  __shared__ __align__(16) T HS[HSN];
+  const int64_t nitems = a.bin_item0[a.bin_nblk];
+  const int64_t item = xcd_item(blockIdx.x, nitems);
+  if (item >= nitems) return;
+  const int bi = find_block(a.bin_item0, a.bin_nblk, item);
+  const int b = a.bin_blocks[bi];
+  int64_t rel = item - a.bin_item0[bi];
+  const int tc = (int)(rel % a.nchunk);
+  rel /= a.nchunk;
+  const int ct = (int)(rel % a.ntile);
+  const int pl = (int)(rel / a.ntile);
+  const int nthr = blockDim.x, tid = threadIdx.x;
+  const int c0 = ct * C, cvalid = min(C, a.nb - c0);
+  const int dn = a.blk_dn[b];
+  const int64_t off = a.blk_off[b];
+  const int gp = a.blk_p0[b] + pl;
+  const int gn0 = a.blk_n0[b];
+  const int tlo = tc * nthr * MAXP;
+  if (tlo >= dn) return;  // chunk beyond this block's sector (bins mix sector widths)
+  const int thi = min(dn, tlo + nthr * MAXP);
+  const int ncl = a.ncl;
+  const int rot = Tile<T, C>::rot();
+  T acc[MAXP][C];
+#pragma unroll
+  for (int q = 0; q < MAXP; q++)
+#pragma unroll
+    for (int c = 0; c < C; c++) acc[q][c] = T(0);
+
+  auto stage_row = [&](char* dst, int64_t row0, int rows) __attribute__((always_inline)) {
+    const T* src = a.V + row0 * a.ldv + c0;
+    if constexpr (DMA) stage_dma<T, C>(dst, src, a.ldv, rows);
+    else stage_sync<T, C>(dst, src, a.ldv, rows, cvalid);
+  };
+
+  GroupIt it = next_group(a, b, gp, 0, ldu(a.pj_start, gp * ncl));
+  stage_row(B0, off + (int64_t)pl * dn, dn);
+  if (it.cls < ncl) stage_row(B1, a.blk_off[it.sb] + (int64_t)it.p * a.blk_dn[it.sb], a.blk_dn[it.sb]);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+
+  // own row: neutron-neutron part (single-particle energies included)
+  const int ns0l = a.blk_nslice0[b];
+#pragma unroll
+  for (int q = 0; q < MAXP; q++) {
+    const int n = tlo + q * nthr + tid;
+    if (n < thi) {
+      const int sl = ns0l + n / 64, ln = n % 64;
+      const int base = a.ne_off[sl], wd = a.ne_w[sl];
+      for (int k = 0; k < wd; k++) {
+        const int at = base + k * 64 + ln;
+        gather<T, C>(acc[q], a.ne_val[at], B0, a.ne_col[at], rot);
+      }
+    }
+  }
+  __syncthreads();
+
+  // proton-neutron part
+  int2 er[MAXP][MAXE];
+  int eb[MAXP], ec[MAXP];
+  int cur = -1, j0c = 0, hn = 0;
+  bool hs_lds = false;
+  const T* hg = a.h;
+  auto step = [&](const char* rd, char* wr) __attribute__((always_inline)) {
+    if (it.cls != cur) {  // new class: neutron jumps to registers, class-table rows to LDS
+      cur = it.cls;
+      const int cn = (2 * a.tjmax - cur / 2) * 2 + (cur & 1);
+      const int* ns0 = a.nj_start + (int64_t)cn * (a.nn_total + 1) + gn0;
+#pragma unroll
+      for (int q = 0; q < MAXP; q++) {
+        const int n = tlo + q * nthr + tid;
+        eb[q] = n < thi ? ns0[n] : 0;
+        ec[q] = n < thi ? ns0[n + 1] - eb[q] : 0;
+#pragma unroll
+        for (int i = 0; i < MAXE; i++) {
+          er[q][i] = make_int2(0, 0);
+          if (i < ec[q]) er[q][i] = a.nj_pack[eb[q] + i];
+          // pin the loads here (before the barrier and the next DMA), not next to their first use
+          asm volatile("" ::"v"(er[q][i].x), "v"(er[q][i].y));
+        }
+      }
+      j0c = ldu(a.pj_start, gp * ncl + cur);
+      const int nj = ldu(a.pj_start, gp * ncl + cur + 1) - j0c;
+      hn = ldu(a.h_ncol, cur);
+      hg = a.h + ldu(a.h_off, cur);
+      hs_lds = nj * hn <= HSN;
+      if (hs_lds)
+        for (int e = tid; e < nj * hn; e += nthr) {
+          const int jj = e / hn, o = e - jj * hn;
+          HS[e] = hg[(a.pj_meta[j0c + jj] >> 1) * hn + o];
+        }
+      __builtin_amdgcn_s_waitcnt(0);  // entries in registers before any DMA is in flight
+      __syncthreads();
+    }
+    const GroupIt nx = next_group(a, b, gp, it.cls, it.je);
+    if (nx.cls < ncl)
+      stage_row(wr, ldu(a.blk_off, nx.sb) + (int64_t)nx.p * ldu(a.blk_dn, nx.sb), ldu(a.blk_dn, nx.sb));
+    // hr points into LDS or into global memory: two copies of the loop keep every load
+    // typed (a generic pointer would make the compiler wait for the DMA in flight)
+    auto apply = [&](auto hrow) __attribute__((always_inline)) {
+      for (int j = it.jg; j < it.je; j++) {
+        const int pm = ldu(a.pj_meta, j);
+        const auto hr = hrow(j, pm);
+        const int ps = pm & 1;
+#pragma unroll
+        for (int q = 0; q < MAXP; q++) {
+#pragma unroll
+          for (int i = 0; i < MAXE; i++)
+            if (i < ec[q]) {
+              const int2 e = er[q][i];
+              const T hv = hr[e.y >> 1];
+              gather<T, C>(acc[q], ((e.y ^ ps) & 1) ? -hv : hv, rd, e.x, rot);
+            }
+          for (int i = MAXE; i < ec[q]; i++) {
+            const int2 e = a.nj_pack[eb[q] + i];
+            const T hv = hr[e.y >> 1];
+            gather<T, C>(acc[q], ((e.y ^ ps) & 1) ? -hv : hv, rd, e.x, rot);
+          }
+        }
+      }
+    };
+    if (hs_lds)
+      apply([&](int j, int) __attribute__((always_inline)) { return HS + (j - j0c) * hn; });
+    else
+      apply([&](int, int pm) __attribute__((always_inline)) { return hg + (pm >> 1) * hn; });
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    it = nx;
+  };
+  while (it.cls < ncl) {
+    step(B1, B0);
+    if (it.cls >= ncl) break;
+    step(B0, B1);
+  }
+  using L = Tile<T, C>;
+#pragma unroll
+  for (int q = 0; q < MAXP; q++) {
+    const int n = tlo + q * nthr + tid;
+    if (n < thi) {
+      T* w = a.W + (off + (int64_t)pl * dn + n) * a.ldw + c0;
+#pragma unroll
+      for (int t = 0; t < L::CPR; t++) {
+        const int k = (t + rot) & (L::CPR - 1);
+#pragma unroll
+        for (int v = 0; v < L::VPC; v++)
+          if (k * L::VPC + v < cvalid) w[k * L::VPC + v] = acc[q][t * L::VPC + v];
+      }
+    }
+  }
+}
+
+// Columns kernel: proton-proton part, W[:, n] += Hpp V[:, n] for one neutron column n of one
+// block; the column (all proton rows of the block, one column tile) is staged in LDS and one
+// lane owns one target proton row p'.
+template <class T, int C, int MAXP>
+__global__ __launch_bounds__(1024) void hv_cols_kernel(HVArgs<T> a) {
+  extern __shared__ __align__(16) char smem_[];
+  constexpr int RS = row_stride<T, C>();
+  T* colv = reinterpret_cast<T*>(smem_);
+  const int64_t nitems = a.citem0[a.nblocks];
+  const int64_t item = xcd_item(blockIdx.x, nitems);
+  if (item >= nitems) return;
+  const int b = find_block(a.citem0, a.nblocks, item);
+  int64_t rel = item - a.citem0[b];
+  const int tc = (int)(rel % a.nchunk);
+  rel /= a.nchunk;
+  const int ct = (int)(rel % a.ntile);
+  const int n = (int)(rel / a.ntile);
+  const int nthr = blockDim.x, tid = threadIdx.x;
+  const int c0 = ct * C, cvalid = min(C, a.nb - c0);
+  const int dn = a.blk_dn[b], dp = a.blk_dp[b];
+  const int64_t off = a.blk_off[b];
+  stage<T, C>(colv, a.V + (off + n) * a.ldv + c0, (int64_t)dn * a.ldv, dp, cvalid);
+  __syncthreads();
+  const int tlo = tc * nthr * MAXP;
+#pragma unroll
+  for (int q = 0; q < MAXP; q++) {
+    const int p = tlo + q * nthr + tid;
+    if (p < dp) {
+      T acc[C];
+#pragma unroll
+      for (int c = 0; c < C; c++) acc[c] = T(0);
+      const int sl = a.blk_pslice0[b] + p / 64, ln = p % 64;
+      const int base = a.pe_off[sl], wd = a.pe_w[sl];
+      for (int k = 0; k < wd; k++) {
+        const int at = base + k * 64 + ln;
+        axpy_row<T, C>(acc, a.pe_val[at], colv + a.pe_col[at] * RS);
+      }
+      T* w = a.W + (off + (int64_t)p * dn + n) * a.ldw + c0;
+#pragma unroll
+      for (int c = 0; c < C; c++)
+        if (c < cvalid) w[c] += acc[c];
+    }
+  }
+}
+
+template <class T, int C, int NTB, int RB>
+static void launch_rows(const HVArgs<T>& a, const HVBin& B, hipStream_t s) {
+  const dim3 grid((unsigned)((B.items + 7) / 8 * 8)), block(B.nthr);
+  if (a.dma) hipLaunchKernelGGL((hv_rows_kernel<T, C, NTB, RB, true>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((hv_rows_kernel<T, C, NTB, RB, false>), grid, block, 0, s, a);
+}
+template <class T, int C, int MP>
+static void launch_cols(const HVArgs<T>& a, const HVPlan& P, hipStream_t s) {
+  hipLaunchKernelGGL((hv_cols_kernel<T, C, MP>), dim3((unsigned)((P.cols_items + 7) / 8 * 8)), dim3(P.nthr_c),
+                     P.shm_c, s, a);
+}
+
+template <class T, int C>
+static void dispatch_c(HVArgs<T>& a, const HVPlan& P, hipStream_t s) {
+  for (const auto& Bp : P.bins) {
+    const HVBin& B = *Bp;
+    a.nchunk = B.nchunk;
+    a.bin_blocks = B.blocks.as<int>();
+    a.bin_item0 = B.item0.as<int64_t>();
+    a.bin_nblk = B.nblk;
+    const bool small = B.rb_kb <= 24;
+    if (B.ntb == 256) small ? launch_rows<T, C, 256, 24>(a, B, s) : launch_rows<T, C, 256, 72>(a, B, s);
+    else if (B.ntb == 768) small ? launch_rows<T, C, 768, 24>(a, B, s) : launch_rows<T, C, 768, 72>(a, B, s);
+    else small ? launch_rows<T, C, 1024, 24>(a, B, s) : launch_rows<T, C, 1024, 72>(a, B, s);
+  }
+  a.nchunk = P.nchunk_c;
+  if (P.maxp_c == 1) launch_cols<T, C, 1>(a, P, s);
+  else if (P.maxp_c == 2) launch_cols<T, C, 2>(a, P, s);
+  else launch_cols<T, C, 4>(a, P, s);
+}
+
+// All launches of one block H.V (rows kernel per bin, then the columns kernel).
+template <class T>
+void dispatch_hv(HVArgs<T>& a, const HVPlan& P, hipStream_t s) {
+  if constexpr (sizeof(T) == 8) {
+    switch (P.C) {
+      case 2: dispatch_c<T, 2>(a, P, s); break;
+      case 4: dispatch_c<T, 4>(a, P, s); break;
+      case 8: dispatch_c<T, 8>(a, P, s); break;
+      default: dispatch_c<T, 16>(a, P, s); break;
+    }
+  } else {
+    switch (P.C) {
+      case 4: dispatch_c<T, 4>(a, P, s); break;
+      case 8: dispatch_c<T, 8>(a, P, s); break;
+      case 16: dispatch_c<T, 16>(a, P, s); break;
+      default: dispatch_c<T, 32>(a, P, s); break;
+    }
+  }
+}
+
+}  // namespace trbl

@@ -113,12 +113,20 @@ struct DeviceTables {
   DevBuf h_term;            // per pn table entry: m-scheme pn term id (-1 if none)
 };
 
-// Work decomposition of one block H.V launch (hv.hip), owned by the model.
+// Work decomposition of one block H.V (hv.hip), owned by the model. The rows kernel is
+// launched once per bin of blocks with similar neutron-sector size, so that the LDS
+// reservation and the workgroup width fit the sector.
+struct HVBin {
+  int nthr = 64, ntb = 256, nchunk = 1, rb_kb = 24, nblk = 0;  // width, its launch bound, chunks, LDS row KB
+  int64_t items = 0;
+  DevBuf blocks, item0;  // block ids of the bin, first work item of each (nblk + 1)
+};
 struct HVPlan {
-  int C = 1, ntile = 1, nchunk_r = 1, nchunk_c = 1, maxp_r = 1, maxp_c = 1, nthr_r = 64, nthr_c = 64;
-  int64_t rows_items = 0, cols_items = 0;
-  size_t shm_r = 0, shm_c = 0, row_bytes = 0, ent_bytes = 0, hs_bytes = 0;
-  DevBuf item0, citem0;
+  int C = 1, ntile = 1, nchunk_c = 1, maxp_c = 1, nthr_c = 64;
+  int64_t cols_items = 0;
+  size_t shm_c = 0;
+  DevBuf citem0;
+  std::vector<std::unique_ptr<HVBin>> bins;
 };
 
 struct MTerm {  // m-scheme two-body term c+_a c+_b c_d c_c (species-local state indices)
@@ -152,7 +160,7 @@ struct Model {
   int pj_count = 0, nj_count = 0;
   int max_dn = 0, max_dp = 0;
   std::vector<int> h_off_host, h_ncol_host;
-  std::vector<int64_t> blk_item0_host;  // prefix of rows per block (for row kernels)
+  std::vector<int> src_blk_host;        // per (block, class): source block or -1
   std::vector<int> sec_slice0[2];       // per species sector: first sliced-ELL slice
 };
 

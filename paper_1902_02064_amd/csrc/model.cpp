@@ -245,6 +245,7 @@ void build_model(Model& m, const trbl_orbit* orbits, int n_orbits, int n_prot, i
     }
   }
   m.dt.src_blk.upload(src);
+  m.src_blk_host = src;
   m.has_h = false;
 }
 

@@ -133,3 +133,25 @@ def test_grad_sd66_full_size_golden():
     err = np.abs(got - ref).max()
     say("sd66 grad max abs diff", err, "scale", np.abs(ref).max())
     assert err <= 1e-7 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("keep", [True, False])
+def test_autograd_function(sd22, keep):
+    """torch.autograd through the eigenvalues: backward = the density kernel, with eigenvectors kept or
+    recomputed; loss sum_k w_k E_k gives the same gradient as trbl_tbme_grad and the oracle."""
+    import paper_1902_02064_amd as trbl
+    w, tb, g, o = sd22
+    n = 6
+    wt = grad_weights(n, 9)
+    v = torch.tensor([t[6] for t in tb], dtype=torch.float64, requires_grad=True)
+    sp = torch.tensor(w.spe, dtype=torch.float64, requires_grad=True)
+    sn = torch.tensor(w.spe, dtype=torch.float64, requires_grad=True)
+    E = trbl.eigenvalues(g, tb, v, sp, sn, nb=4, n_eig=n, l_s=12, l_m=40, tol=1e-11, keep_vectors=keep)
+    loss = (torch.from_numpy(wt) * E).sum()
+    loss.backward()
+    ov, os_, e = _oracle_grad(o, tb, n, wt)
+    assert np.abs(E.detach().numpy() - e).max() <= 1e-9 * np.abs(e).max()
+    say("autograd keep", keep, "max diff", np.abs(v.grad.numpy() - ov).max())
+    assert np.abs(v.grad.numpy() - ov).max() <= 1e-8 * np.abs(ov).max()
+    assert np.abs(sp.grad.numpy() - os_[:3]).max() <= 1e-8 * np.abs(os_).max()
+    assert np.abs(sn.grad.numpy() - os_[3:]).max() <= 1e-8 * np.abs(os_).max()
