@@ -41,7 +41,7 @@ def parse():
     p.add_argument("--hv-only", action="store_true", help="only the H.V timing loop (for profilers)")
     p.add_argument("--calib-copy", action="store_true",
                    help="with --hv-only: also run a plain 1 GiB device copy (counter calibration)")
-    p.add_argument("--check-every", type=int, default=4)
+    p.add_argument("--check-every", type=int, default=-1, help="convergence-test period; -1 = adaptive")
     return p.parse_args()
 
 

@@ -85,7 +85,9 @@ typedef struct {
   const void* v0;  /* optional device start block [D][nb] (FP64 or FP32 per precision); NULL = random */
   void* stream;    /* hipStream_t; NULL = default stream */
   int check_every; /* diagonalise T for the convergence test every k iterations (and at every
-                      restart); 0 or 1 = every iteration, as in Alg. 4 */
+                      restart); 0 or 1 = every iteration, as in Alg. 4; negative = adaptive:
+                      the next test is scheduled from the observed decay of the largest
+                      residual (every restart still tests) */
 } trbl_opts;
 
 typedef struct {

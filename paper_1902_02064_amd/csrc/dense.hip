@@ -45,22 +45,29 @@ __device__ __forceinline__ void ld4(const T* p, int valid, double out[4]) {
 
 // ------------------------------------------------------------------ C = A^T B (partial per workgroup)
 // A: [D][lda] (m columns used), B: [D][ldb] (nb columns). part[g] is m x nb row-major.
-template <class TA, class TB, int MAXI, int MAXC>
-__global__ __launch_bounds__(512) void tn_partial_kernel(const TA* __restrict__ A, int64_t lda, int m,
+// Workgroup (x, y) covers a row chunk and the column chunk [64 NP y, 64 NP (y + 1)) of A; each
+// wave takes row quads of the chunk. In a 64-column panel, lane l loads 4 consecutive
+// values A[r][c0 + 4 (l % 16) + t] of row r = 4-row quad + l / 16 (32 bytes), and value t
+// feeds MFMA t, whose output row i then stands for column c0 + 4 i + t.
+template <class TA, class TB, int NP, int MAXC>
+__global__ __launch_bounds__(256) void tn_partial_kernel(const TA* __restrict__ A, int64_t lda, int m,
                                                          const TB* __restrict__ B, int64_t ldb, int nb, int64_t D,
                                                          int64_t rows_per, double* __restrict__ part) {
-  constexpr int WAVES = 8;
+  constexpr int WAVES = 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int mt = (m + 15) >> 4, ct = (nb + 15) >> 4;
-  d4 acc[MAXI][MAXC];
+  const int ct = (nb + 15) >> 4;
+  const int cbase = blockIdx.y * 64 * NP;
+  d4 acc[NP][4][MAXC];
 #pragma unroll
-  for (int i = 0; i < MAXI; i++)
+  for (int p = 0; p < NP; p++)
 #pragma unroll
-    for (int q = 0; q < MAXC; q++) acc[i][q] = d4{0, 0, 0, 0};
+    for (int t = 0; t < 4; t++)
+#pragma unroll
+      for (int q = 0; q < MAXC; q++) acc[p][t][q] = d4{0, 0, 0, 0};
   const int64_t r0 = (int64_t)blockIdx.x * rows_per;
   const int64_t r1 = min(D, r0 + rows_per);
   const int li = lane & 15, lk = lane >> 4;
-  for (int64_t r = r0; r < r1; r += 4) {
+  for (int64_t r = r0 + 4 * wave; r < r1; r += 4 * WAVES) {
     const int64_t rr = r + lk;
     const bool rok = rr < r1;
     double bop[MAXC];
@@ -70,40 +77,63 @@ __global__ __launch_bounds__(512) void tn_partial_kernel(const TA* __restrict__ 
       bop[q] = (q < ct && rok && c < nb) ? ld(B + rr * ldb + c) : 0.0;
     }
 #pragma unroll
-    for (int ti = 0; ti < MAXI; ti++) {
-      const int it = wave + ti * WAVES;
-      if (it < mt) {
-        const int i = it * 16 + li;
-        const double aop = (rok && i < m) ? ld(A + rr * lda + i) : 0.0;
+    for (int p = 0; p < NP; p++) {
+      const int c0 = cbase + 64 * p + 4 * li;
+      double a4[4];
+      if (rok && c0 < m) ld4(A + rr * lda + c0, m - c0, a4);
+      else a4[0] = a4[1] = a4[2] = a4[3] = 0.0;
+#pragma unroll
+      for (int t = 0; t < 4; t++)
 #pragma unroll
         for (int q = 0; q < MAXC; q++)
-          if (q < ct) acc[ti][q] = mfma(aop, bop[q], acc[ti][q]);
-      }
+          if (q < ct) acc[p][t][q] = mfma(a4[t], bop[q], acc[p][t][q]);
     }
   }
-  double* out = part + (int64_t)blockIdx.x * m * nb;
+  // combine the waves' sums in LDS (one wave after the other), then write the chunk's partial
+  constexpr int NBS = 16 * MAXC;
+  __shared__ double red[64 * NP * NBS];
+  const int ncol = min(64 * NP, m - cbase);
+  for (int e = threadIdx.x; e < 64 * NP * NBS; e += blockDim.x) red[e] = 0.0;
+  for (int w = 0; w < WAVES; w++) {
+    __syncthreads();
+    if (wave != w) continue;
 #pragma unroll
-  for (int ti = 0; ti < MAXI; ti++) {
-    const int it = wave + ti * WAVES;
-    if (it >= mt) continue;
+    for (int p = 0; p < NP; p++)
 #pragma unroll
-    for (int q = 0; q < MAXC; q++) {
-      if (q >= ct) continue;
+      for (int t = 0; t < 4; t++)
 #pragma unroll
-      for (int v = 0; v < 4; v++) {
-        const int i = it * 16 + lk + 4 * v, c = q * 16 + li;
-        if (i < m && c < nb) out[i * nb + c] = acc[ti][q][v];
-      }
-    }
+        for (int q = 0; q < MAXC; q++) {
+          if (q >= ct) continue;
+#pragma unroll
+          for (int v = 0; v < 4; v++) {
+            const int col = 64 * p + 4 * (lk + 4 * v) + t, c = q * 16 + li;
+            if (col < ncol && c < nb) red[col * NBS + c] += acc[p][t][q][v];
+          }
+        }
   }
+  __syncthreads();
+  double* out = part + (int64_t)blockIdx.x * m * nb + (int64_t)cbase * nb;
+  for (int e = threadIdx.x; e < ncol * nb; e += blockDim.x) out[e] = red[(e / nb) * NBS + e % nb];
 }
 
-__global__ void reduce_partials_kernel(const double* __restrict__ part, int G, int64_t len, double* __restrict__ out) {
-  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (k >= len) return;
+// out[k] = sum_g part[g * len + k]: 16 outputs per block, 16 threads share the G terms of each
+// (fixed summation order, so results are reproducible)
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __restrict__ part, int G, int64_t len,
+                                                              double* __restrict__ out) {
+  __shared__ double red[16][17];
+  const int kx = threadIdx.x & 15, gy = threadIdx.x >> 4;
+  const int64_t k = (int64_t)blockIdx.x * 16 + kx;
   double s = 0.0;
-  for (int g = 0; g < G; g++) s += part[(int64_t)g * len + k];
-  out[k] = s;
+  if (k < len)
+#pragma unroll 8
+    for (int g = gy; g < G; g += 16) s += part[(int64_t)g * len + k];
+  red[gy][kx] = s;
+  __syncthreads();
+  if (gy == 0 && k < len) {
+    double t = 0.0;
+    for (int j = 0; j < 16; j++) t += red[j][kx];
+    out[k] = t;
+  }
 }
 
 // ------------------------------------------------------------------ Bout = Bin - A C (+ fused partial product)
@@ -257,15 +287,17 @@ template <class TI, class TO>
 __global__ __launch_bounds__(256) void apply_small_kernel(const TI* Bin, int64_t ldi, const double* __restrict__ R,
                                                           TO* Bout, int64_t ldo, int nb, int64_t D, int gram,
                                                           double* __restrict__ part) {
+  // tiles of `rows` rows (rows * nb = 2048 values); thread t owns column t % nb of rows t / nb,
+  // t / nb + 256 / nb, ...; the Gram partial of the tile is formed from the outputs in LDS,
+  // one (i, j) pair per thread.
   extern __shared__ double lds[];
   double* Rs = lds;                 // nb x nb
-  const int rows = max(1, 256 / nb);
+  const int rows = 2048 / nb;
   double* tile = lds + nb * nb;     // rows x nb inputs
   double* outt = tile + rows * nb;  // rows x nb outputs
   for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) Rs[e] = R[e];
   const int npair = nb * nb;
   double g[16];
-  const int gper = (npair + blockDim.x - 1) / blockDim.x;
   for (int q = 0; q < 16; q++) g[q] = 0.0;
   __syncthreads();
   const int64_t ntiles = (D + rows - 1) / rows;
@@ -278,15 +310,16 @@ __global__ __launch_bounds__(256) void apply_small_kernel(const TI* Bin, int64_t
     __syncthreads();
     for (int e = threadIdx.x; e < rows * nb; e += blockDim.x) {
       const int rl = e / nb, c = e % nb;
+      const double* tr = tile + rl * nb;
       double s = 0.0;
-      for (int k = 0; k < nb; k++) s += tile[rl * nb + k] * Rs[k * nb + c];
+      for (int k = 0; k < nb; k++) s += tr[k] * Rs[k * nb + c];
       outt[e] = s;
       const int64_t r = r0 + rl;
       if (r < D) Bout[r * ldo + c] = (TO)s;
     }
-    __syncthreads();
     if (gram) {
-      for (int q = 0; q < gper && q < 16; q++) {
+      __syncthreads();
+      for (int q = 0; q < 16; q++) {
         const int pidx = threadIdx.x + q * blockDim.x;
         if (pidx < npair) {
           const int i = pidx / nb, j = pidx % nb;
@@ -300,7 +333,7 @@ __global__ __launch_bounds__(256) void apply_small_kernel(const TI* Bin, int64_t
   }
   if (gram) {
     double* out = part + (int64_t)blockIdx.x * npair;
-    for (int q = 0; q < gper && q < 16; q++) {
+    for (int q = 0; q < 16; q++) {
       const int pidx = threadIdx.x + q * blockDim.x;
       if (pidx < npair) out[pidx] = g[q];
     }
@@ -526,31 +559,28 @@ static int grid_for(int64_t rows, int64_t rows_per_wg, int cap) {
 template <class TA, class TB>
 void tn(const TA* A, int64_t lda, int m, const TB* B, int64_t ldb, int nb, int64_t D, double* C, Scratch& s,
         hipStream_t st) {
-  TRBL_REQUIRE(m <= 8 * 6 * 16 && nb <= 64, TRBL_E_INVALID, "projection too wide");
-  int G = grid_for(D, 256, 1024);
-  int64_t rows_per = ((D + G - 1) / G + 3) / 4 * 4;
+  TRBL_REQUIRE(m >= 1 && nb >= 1 && nb <= 64, TRBL_E_INVALID, "projection shape out of range");
+  const int ct = (nb + 15) / 16;
+  const int np = ct == 1 ? std::min(2, (m + 63) / 64) : 1;  // panels of 64 columns per workgroup
+  const int ny = (m + 64 * np - 1) / (64 * np);
+  int G = grid_for(D, 512, std::max(64, 1024 / ny));
+  int64_t rows_per = ((D + G - 1) / G + 15) / 16 * 16;
   G = (int)((D + rows_per - 1) / rows_per);
   double* part = s.partials((size_t)G * m * nb);
-  const int mt = (m + 15) / 16, ct = (nb + 15) / 16, mi = (mt + 7) / 8;
-#define TN_LAUNCH(MI, MC)                                                                                     \
-  hipLaunchKernelGGL((tn_partial_kernel<TA, TB, MI, MC>), dim3(G), dim3(512), 0, st, A, lda, m, B, ldb, nb, D, \
-                     rows_per, part)
+  const dim3 grid(G, ny);
+#define TN_LAUNCH(NP, MC) \
+  hipLaunchKernelGGL((tn_partial_kernel<TA, TB, NP, MC>), grid, dim3(256), 0, st, A, lda, m, B, ldb, nb, D, rows_per, part)
   if (ct == 1) {
-    if (mi <= 1) TN_LAUNCH(1, 1);
-    else if (mi <= 2) TN_LAUNCH(2, 1);
-    else if (mi <= 4) TN_LAUNCH(4, 1);
-    else TN_LAUNCH(6, 1);
+    if (np == 1) TN_LAUNCH(1, 1);
+    else TN_LAUNCH(2, 1);
   } else if (ct == 2) {
-    if (mi <= 2) TN_LAUNCH(2, 2);
-    else if (mi <= 4) TN_LAUNCH(4, 2);
-    else TN_LAUNCH(6, 2);
+    TN_LAUNCH(1, 2);
   } else {
-    if (mi <= 2) TN_LAUNCH(2, 4);
-    else TN_LAUNCH(6, 4);
+    TN_LAUNCH(1, 4);
   }
 #undef TN_LAUNCH
   const int64_t len = (int64_t)m * nb;
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, part, G, len, C);
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((len + 15) / 16)), dim3(256), 0, st, part, G, len, C);
   TRBL_HIP(hipGetLastError());
 }
 
@@ -592,7 +622,7 @@ void update(const TA* A, int64_t lda, int m, const double* C, const TI* Bin, int
 #undef UPD_LAUNCH
   if (mode) {
     if (Pout)
-      hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((plen + 255) / 256)), dim3(256), 0, st, part, G,
+      hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((plen + 15) / 16)), dim3(256), 0, st, part, G,
                          plen, Pout);
     s.last_G = G;
     s.last_part = part;
@@ -603,8 +633,8 @@ void update(const TA* A, int64_t lda, int m, const double* C, const TI* Bin, int
 template <class TI, class TO>
 void apply_small(const TI* Bin, int64_t ldi, const double* R, TO* Bout, int64_t ldo, int nb, int64_t D, bool gram,
                  Scratch& s, hipStream_t st) {
-  const int rows = std::max(1, 256 / nb);
-  const int G = grid_for(D, rows * 8, 1024);
+  const int rows = 2048 / nb;
+  const int G = grid_for(D, rows * 4, 1024);
   double* part = gram ? s.partials((size_t)G * nb * nb) : nullptr;
   const size_t shm = (size_t)(nb * nb + 2 * rows * nb) * sizeof(double);
   hipLaunchKernelGGL((apply_small_kernel<TI, TO>), dim3(G), dim3(256), shm, st, Bin, ldi, R, Bout, ldo, nb, D,
@@ -619,6 +649,12 @@ void apply_small(const TI* Bin, int64_t ldi, const double* R, TO* Bout, int64_t 
 void chol(const double* part, int G, int nb, double* R, double* Rinv, const double* Rprev, double* beta, int* status,
           hipStream_t st) {
   const size_t shm = 2 * (size_t)nb * nb * sizeof(double);
+  if (G > 1) {  // sum the partials into slice 0 (each block reads its own columns before writing them)
+    const int64_t len = (int64_t)nb * nb;
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((len + 15) / 16)), dim3(256), 0, st, part, G, len,
+                       const_cast<double*>(part));
+    G = 1;
+  }
   hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(256), shm, st, part, G, nb, R, Rinv, Rprev, beta, status);
   TRBL_HIP(hipGetLastError());
 }

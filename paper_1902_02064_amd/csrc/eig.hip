@@ -16,7 +16,8 @@
 namespace trbl {
 
 constexpr int EIG_THREADS = 1024;
-constexpr int EIG_NMAX = 1024;
+constexpr int EIG_NMAX = 640;  // largest projected matrix (l_m)
+constexpr int PNB = 8;         // Householder panel width
 
 __device__ static double block_sum(double v, double* red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -28,6 +29,11 @@ __device__ static double block_sum(double v, double* red) {
   const int nw = blockDim.x >> 6;
   for (int w = 0; w < nw; w++) s += red[w];
   return s;
+}
+
+__device__ static double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
 }
 
 __device__ static uint64_t mix64(uint64_t z) {
@@ -51,58 +57,124 @@ __device__ static int sturm(const double* d, const double* e2, int n, double x, 
   return cnt;
 }
 
+constexpr int EIG_BIG = 20 * EIG_NMAX;  // shared work area (doubles)
+
 __global__ __launch_bounds__(EIG_THREADS) void symeig_kernel(const double* __restrict__ T, int ldt, int n, int nvec,
-                                                             double* __restrict__ theta, double* __restrict__ U,
-                                                             int ldu, double* __restrict__ A, double* __restrict__ Z,
-                                                             double* __restrict__ LU) {
+                                                             int orth, double* __restrict__ theta,
+                                                             double* __restrict__ U, int ldu, double* __restrict__ A,
+                                                             double* __restrict__ Z, double* __restrict__ LU) {
+  // work area: panel vectors of the blocked reduction, then row chunks of Z (Cholesky QR),
+  // then a column block of Z plus staged reflectors (back-transformation)
+  __shared__ double big[EIG_BIG];
+  double(*Vp)[EIG_NMAX] = reinterpret_cast<double(*)[EIG_NMAX]>(big);
+  double(*Wp)[EIG_NMAX] = reinterpret_cast<double(*)[EIG_NMAX]>(big + PNB * EIG_NMAX);
   __shared__ double d[EIG_NMAX], e[EIG_NMAX], e2[EIG_NMAX], vv[EIG_NMAX], pw[EIG_NMAX], lam[EIG_NMAX];
-  __shared__ double red[32], wlo[16], whi[16], wnm[16];
+  __shared__ double part[EIG_THREADS], sx[EIG_THREADS];
+  __shared__ int scnt[EIG_THREADS];
+  __shared__ double red[32], wlo[16], whi[16], wnm[16], xw[PNB], yv[PNB];
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6, nwave = nthr >> 6;
 
-  for (int64_t q = tid; q < (int64_t)n * n; q += nthr) A[q] = T[(q / n) * ldt + q % n];
+  for (int r = wave; r < n; r += nwave)
+    for (int c = lane; c < n; c += 64) A[(int64_t)r * n + c] = T[(int64_t)r * ldt + c];
   __syncthreads();
 
-  // ---- 1. Householder tridiagonalisation (lower); reflector k is stored in row k of A
-  for (int k = 0; k + 2 < n; k++) {
-    const int len = n - k - 1;
-    const double* row = A + (int64_t)k * n + k + 1;
-    double s = 0.0;
-    for (int i = tid; i < len; i += nthr) s += row[i] * row[i];
-    const double s2 = block_sum(s, red);
-    const double x0 = row[0];
-    const double sigma = sqrt(s2);
-    if (tid == 0) d[k] = A[(int64_t)k * n + k];
-    if (sigma == 0.0) {
+  // ---- 1. Householder tridiagonalisation, blocked in panels of PNB columns. Inside a panel
+  // the trailing matrix is not updated; its product with v is corrected by the panel's
+  // earlier (v_t, w_t) pairs, A_cur = A_panel_start - sum_t (v_t w_t^T + w_t v_t^T). After the
+  // panel the trailing block receives the rank-2*PNB update at once. Reflector j (H_j =
+  // I - 2 v v^T, |v| = 1, acting on rows j+1..n-1) is kept in row j of A.
+  for (int k0 = 0; k0 + 2 < n; k0 += PNB) {
+    const int nbp = min(PNB, n - 2 - k0);
+    for (int i = 0; i < nbp; i++) {
+      const int j = k0 + i;
+      const int len = n - j - 1;
+      // column j (rows j..n-1) of the current matrix
+      for (int r = tid; r <= len; r += nthr) {
+        const int rr = j + r;
+        double a = A[(int64_t)j * n + rr];
+        for (int t = 0; t < i; t++) a -= Vp[t][rr] * Wp[t][j] + Wp[t][rr] * Vp[t][j];
+        vv[r] = a;
+      }
       __syncthreads();
-      if (tid == 0) e[k] = 0.0;
-      for (int i = tid; i < len; i += nthr) A[(int64_t)k * n + k + 1 + i] = 0.0;
+      double s = 0.0;
+      for (int r = tid; r < len; r += nthr) s += vv[1 + r] * vv[1 + r];
+      const double s2 = block_sum(s, red);
+      const double x0 = vv[1];
+      const double sigma = sqrt(s2);
+      if (tid == 0) d[j] = vv[0];
+      if (sigma == 0.0) {
+        for (int r = tid; r < n; r += nthr) {
+          Vp[i][r] = 0.0;
+          Wp[i][r] = 0.0;
+          if (r > j) A[(int64_t)j * n + r] = 0.0;
+        }
+        if (tid == 0) e[j] = 0.0;
+        __syncthreads();
+        continue;
+      }
+      const double alpha = (x0 > 0.0) ? -sigma : sigma;
+      const double vn = sqrt(s2 - x0 * x0 + (x0 - alpha) * (x0 - alpha));
+      for (int r = tid; r < n; r += nthr) Vp[i][r] = r <= j ? 0.0 : (r == j + 1 ? x0 - alpha : vv[r - j]) / vn;
+      if (tid == 0) e[j] = alpha;
       __syncthreads();
-      continue;
+      // p = A_panel_start[j+1:, j+1:] v. A is symmetric, so p[c] = sum_r A[r][c] v[r]: a thread
+      // owns column c (coalesced row reads) and the rows are split over ng groups whose partial
+      // sums meet in LDS. Then the dots of the earlier panel vectors with v.
+      const double* vi = &Vp[i][j + 1];
+      const int cp = (len + 63) & ~63;
+      const int ng = max(1, nthr / cp);
+      {
+        const int g = tid / cp, c = tid - (tid / cp) * cp;
+        if (g < ng && c < len) {
+          const double* ac = A + (int64_t)(j + 1) * n + j + 1 + c;
+          double t = 0.0;
+#pragma unroll 8
+          for (int r = g; r < len; r += ng) t += ac[(int64_t)r * n] * vi[r];
+          part[g * cp + c] = t;
+        }
+      }
+      for (int q = wave; q < 2 * i; q += nwave) {
+        const double* u = (q < i) ? &Wp[q][j + 1] : &Vp[q - i][j + 1];
+        double t = 0.0;
+        for (int c = lane; c < len; c += 64) t += u[c] * vi[c];
+        t = wave_sum(t);
+        if (lane == 0) (q < i ? xw[q] : yv[q - i]) = t;
+      }
+      __syncthreads();
+      double kp = 0.0;
+      for (int r = tid; r < len; r += nthr) {
+        const int rr = j + 1 + r;
+        double p = 0.0;
+        for (int g = 0; g < ng; g++) p += part[g * cp + r];
+        for (int t = 0; t < i; t++) p -= Vp[t][rr] * xw[t] + Wp[t][rr] * yv[t];
+        pw[r] = p;
+        kp += vi[r] * p;
+      }
+      const double K = block_sum(kp, red);
+      for (int r = tid; r < n; r += nthr) {
+        Wp[i][r] = r <= j ? 0.0 : 2.0 * pw[r - j - 1] - 2.0 * K * Vp[i][r];
+        if (r > j) A[(int64_t)j * n + r] = Vp[i][r];
+      }
+      __syncthreads();
     }
-    const double alpha = (x0 > 0.0) ? -sigma : sigma;
-    const double vn = sqrt(s2 - x0 * x0 + (x0 - alpha) * (x0 - alpha));
-    for (int i = tid; i < len; i += nthr) vv[i] = (i == 0 ? (x0 - alpha) : row[i]) / vn;
-    if (tid == 0) e[k] = alpha;
-    __syncthreads();
-    for (int i = wave; i < len; i += nwave) {  // p = A_sub v, one wave per row
-      const double* ar = A + (int64_t)(k + 1 + i) * n + k + 1;
-      double t = 0.0;
-      for (int j = lane; j < len; j += 64) t += ar[j] * vv[j];
-      for (int o = 32; o > 0; o >>= 1) t += __shfl_down(t, o, 64);
-      if (lane == 0) pw[i] = t;
+    // trailing update of rows / columns >= k0 + nbp
+    const int s0 = k0 + nbp;
+    for (int r = s0 + wave; r < n; r += nwave) {
+      double vr[PNB], wr[PNB];
+#pragma unroll
+      for (int t = 0; t < PNB; t++) {
+        vr[t] = t < nbp ? Vp[t][r] : 0.0;
+        wr[t] = t < nbp ? Wp[t][r] : 0.0;
+      }
+      double* ar = A + (int64_t)r * n;
+      for (int c = s0 + lane; c < n; c += 64) {
+        double a = ar[c];
+#pragma unroll
+        for (int t = 0; t < PNB; t++) a -= vr[t] * Wp[t][c] + wr[t] * Vp[t][c];
+        ar[c] = a;
+      }
     }
-    __syncthreads();
-    double kp = 0.0;
-    for (int i = tid; i < len; i += nthr) kp += vv[i] * pw[i];
-    const double K = block_sum(kp, red);
-    for (int i = tid; i < len; i += nthr) pw[i] = 2.0 * pw[i] - 2.0 * K * vv[i];
-    __syncthreads();
-    for (int64_t q = tid; q < (int64_t)len * len; q += nthr) {
-      const int i = (int)(q / len), j = (int)(q % len);
-      A[(int64_t)(k + 1 + i) * n + k + 1 + j] -= vv[i] * pw[j] + pw[i] * vv[j];
-    }
-    for (int i = tid; i < len; i += nthr) A[(int64_t)k * n + k + 1 + i] = vv[i];
     __syncthreads();
   }
   if (tid == 0) {
@@ -147,19 +219,45 @@ __global__ __launch_bounds__(EIG_THREADS) void symeig_kernel(const double* __res
   glo -= 2.0 * DBL_EPSILON * tnorm * n + pivmin;
   ghi += 2.0 * DBL_EPSILON * tnorm * n + pivmin;
 
-  // ---- 2. bisection: thread t < nvec finds eigenvalue t; thread nvec finds the largest
-  const int want = (tid < nvec) ? tid : ((tid == nvec && nvec < n) ? n - 1 : -1);
-  if (want >= 0) {
+  // ---- 2. eigenvalues by multisection: a group of tpe threads refines one eigenvalue (the
+  // nvec lowest and the largest); each round its threads take Sturm counts at tpe interior
+  // points of the group's interval, which shrinks by a factor tpe + 1.
+  {
+    const int nwant = nvec < n ? nvec + 1 : nvec;
+    const int tpe = max(1, min(32, nthr / nwant));
+    const int q = tid / tpe, sub = tid - (tid / tpe) * tpe;
+    const int want = q < nvec ? q : ((q == nvec && nvec < n) ? n - 1 : -1);
     double lo = glo, hi = ghi;
-    for (int it = 0; it < 200; it++) {
-      const double mid = 0.5 * (lo + hi);
-      if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + 2.0 * pivmin || mid == lo || mid == hi) break;
-      if (sturm(d, e2, n, mid, pivmin) > want) hi = mid;
-      else lo = mid;
+    const int rounds = (int)ceil(64.0 / log2((double)tpe + 1.0)) + 1;
+    for (int rd = 0; rd < rounds; rd++) {
+      const bool live =
+          want >= 0 && !(hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + 2.0 * pivmin);
+      double x = lo;
+      int cnt = -1;
+      if (live) {
+        x = lo + (hi - lo) * (double)(sub + 1) / (double)(tpe + 1);
+        cnt = sturm(d, e2, n, x, pivmin);
+      }
+      sx[tid] = x;
+      scnt[tid] = cnt;
+      __syncthreads();
+      if (live) {
+        double nlo = lo, nhi = hi;
+        for (int t = 0; t < tpe; t++) {
+          const double xt = sx[q * tpe + t];
+          if (scnt[q * tpe + t] > want) nhi = fmin(nhi, xt);
+          else nlo = fmax(nlo, xt);
+        }
+        lo = nlo;
+        hi = nhi;
+      }
+      __syncthreads();
     }
-    const double l = 0.5 * (lo + hi);
-    if (want < n) lam[want] = l;
-    theta[want] = l;
+    if (want >= 0 && sub == 0) {
+      const double l = 0.5 * (lo + hi);
+      lam[want] = l;
+      theta[want] = l;
+    }
   }
   __syncthreads();
 
@@ -250,68 +348,135 @@ __global__ __launch_bounds__(EIG_THREADS) void symeig_kernel(const double* __res
 #undef AT
   }
   __syncthreads();
-  // Cholesky QR, twice, of Z (n x nvec): G = Z^T Z in A's space (A rows are still needed:
-  // the reflectors live in the upper part, so use LU's storage for G and R).
-  double* G = LU;  // nvec x nvec
-  for (int pass = 0; pass < 2 && nvec > 1; pass++) {
-    for (int64_t q = tid; q < (int64_t)nvec * nvec; q += nthr) {
-      const int r = (int)(q / nvec), c = (int)(q % nvec);
-      if (c < r) continue;
-      double s = 0.0;
-      for (int i = 0; i < n; i++) s += Z[(int64_t)i * nvec + r] * Z[(int64_t)i * nvec + c];
-      G[(int64_t)r * nvec + c] = s;
+  // Cholesky QR, twice, of Z (n x nvec, row-major), when orthonormal vectors are needed
+  // (restarts, final vectors). G = Z^T Z from row chunks of Z staged in LDS.
+  double* G = LU;  // nvec x nvec (upper triangle)
+  for (int pass = 0; pass < 2 && orth && nvec > 1; pass++) {
+    const int nt = (nvec + 3) / 4;
+    const int RC = min(n, EIG_BIG / nvec);
+    for (int t0 = 0; t0 < nt * nt; t0 += nthr) {
+      const int tt = t0 + tid;
+      const int rt = tt / nt, ct = tt - (tt / nt) * nt;
+      const bool mine = tt < nt * nt && ct >= rt;
+      const int r0 = rt * 4, c0 = ct * 4;
+      double acc[4][4] = {};
+      for (int i0 = 0; i0 < n; i0 += RC) {
+        const int rc = min(RC, n - i0);
+        __syncthreads();
+        for (int q = tid; q < rc * nvec; q += nthr) big[q] = Z[(int64_t)i0 * nvec + q];
+        __syncthreads();
+        if (mine)
+          for (int i = 0; i < rc; i++) {
+            const double* zr = big + i * nvec;
+            double zl[4], zc[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+              zl[q] = r0 + q < nvec ? zr[r0 + q] : 0.0;
+              zc[q] = c0 + q < nvec ? zr[c0 + q] : 0.0;
+            }
+#pragma unroll
+            for (int a = 0; a < 4; a++)
+#pragma unroll
+              for (int b = 0; b < 4; b++) acc[a][b] += zl[a] * zc[b];
+          }
+      }
+      if (mine)
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+          for (int b = 0; b < 4; b++)
+            if (r0 + a < nvec && c0 + b < nvec && c0 + b >= r0 + a) G[(int64_t)(r0 + a) * nvec + c0 + b] = acc[a][b];
     }
     __syncthreads();
     // upper Cholesky G = R^T R in place (row k finalised at step k)
     for (int k = 0; k < nvec; k++) {
-      if (tid == 0) G[(int64_t)k * nvec + k] = sqrt(fmax(G[(int64_t)k * nvec + k], 1e-300));
+      const double rkk = sqrt(fmax(G[(int64_t)k * nvec + k], 1e-300));
       __syncthreads();
-      const double rkk = G[(int64_t)k * nvec + k];
       for (int c = k + 1 + tid; c < nvec; c += nthr) G[(int64_t)k * nvec + c] /= rkk;
+      if (tid == 0) G[(int64_t)k * nvec + k] = rkk;
       __syncthreads();
-      for (int64_t q = tid; q < (int64_t)(nvec - k - 1) * (nvec - k - 1); q += nthr) {
-        const int r = k + 1 + (int)(q / (nvec - k - 1)), c = k + 1 + (int)(q % (nvec - k - 1));
-        if (c >= r) G[(int64_t)r * nvec + c] -= G[(int64_t)k * nvec + r] * G[(int64_t)k * nvec + c];
+      for (int r = k + 1 + wave; r < nvec; r += nwave) {
+        const double gkr = G[(int64_t)k * nvec + r];
+        for (int c = r + lane; c < nvec; c += 64) G[(int64_t)r * nvec + c] -= gkr * G[(int64_t)k * nvec + c];
       }
       __syncthreads();
     }
-    // Z <- Z R^-1: each row of Z solves x R = z (forward over columns)
-    for (int i = tid; i < n; i += nthr) {
-      double* zr = Z + (int64_t)i * nvec;
-      for (int c = 0; c < nvec; c++) {
-        double s = zr[c];
-        for (int r = 0; r < c; r++) s -= zr[r] * G[(int64_t)r * nvec + c];
-        zr[c] = s / G[(int64_t)c * nvec + c];
+    // Z <- Z R^-1 by chunks of 64 rows in LDS; 16 lanes of one wave share a row: x R = z is
+    // solved column by column, each dot split over the 16 lanes
+    const int RZ = min(nthr / 16, EIG_BIG / nvec);
+    for (int i0 = 0; i0 < n; i0 += RZ) {
+      const int rr = min(RZ, n - i0);
+      for (int q = tid; q < rr * nvec; q += nthr) big[q] = Z[(int64_t)i0 * nvec + q];
+      __syncthreads();
+      const int row = tid >> 4, sub = tid & 15;
+      if (row < rr) {
+        double* zr = big + row * nvec;
+        for (int c = 0; c < nvec; c++) {
+          double s = 0.0;
+          for (int r = sub; r < c; r += 16) s += zr[r] * G[(int64_t)r * nvec + c];
+          for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
+          const double val = (zr[c] - s) / G[(int64_t)c * nvec + c];
+          __builtin_amdgcn_wave_barrier();
+          if (sub == 0) zr[c] = val;
+          __builtin_amdgcn_wave_barrier();
+        }
       }
+      __syncthreads();
+      for (int q = tid; q < rr * nvec; q += nthr) Z[(int64_t)i0 * nvec + q] = big[q];
+      __syncthreads();
     }
-    __syncthreads();
   }
 
-  // ---- 4. back-transformation U = H_0 H_1 ... H_{n-3} Z (apply reflectors last to first)
-  for (int k = n - 3; k >= 0; k--) {
-    const int len = n - k - 1;
-    for (int i = tid; i < len; i += nthr) vv[i] = A[(int64_t)k * n + k + 1 + i];
-    __syncthreads();
-    for (int j = tid; j < nvec; j += nthr) {
-      double s = 0.0;
-      for (int i = 0; i < len; i++) s += vv[i] * Z[(int64_t)(k + 1 + i) * nvec + j];
-      s *= 2.0;
-      for (int i = 0; i < len; i++) Z[(int64_t)(k + 1 + i) * nvec + j] -= s * vv[i];
+  // ---- 4. back-transformation U = H_0 H_1 ... H_{n-3} Z (reflectors applied last to first):
+  // blocks of 16 columns in LDS, one wave per column; nr reflectors at a time are staged in
+  // LDS (zero-padded to full length) between barriers.
+  {
+    double* zs = big;
+    double* vb = big + 16 * n;
+    const int nr = max(1, min(16, (EIG_BIG - 16 * n) / n));
+    for (int cb = 0; cb < nvec; cb += 16) {
+      const int ncol = min(16, nvec - cb);
+      for (int q = tid; q < n * ncol; q += nthr) {
+        const int i = q / ncol, c = q - (q / ncol) * ncol;
+        zs[c * n + i] = Z[(int64_t)i * nvec + cb + c];
+      }
+      for (int k0 = n - 3; k0 >= 0; k0 -= nr) {
+        __syncthreads();
+        for (int q = tid; q < nr * n; q += nthr) {
+          const int t = q / n, i = q - (q / n) * n, k = k0 - t;
+          vb[q] = (k >= 0 && i > k) ? A[(int64_t)k * n + i] : 0.0;
+        }
+        __syncthreads();
+        if (wave < ncol) {
+          double* z = zs + wave * n;
+          for (int t = 0; t < nr && k0 - t >= 0; t++) {
+            const int k = k0 - t;
+            const double* v = vb + t * n;
+            double sdot = 0.0;
+            for (int i = k + 1 + lane; i < n; i += 64) sdot += v[i] * z[i];
+            sdot = 2.0 * wave_sum(sdot);
+            for (int i = k + 1 + lane; i < n; i += 64) z[i] -= sdot * v[i];
+          }
+        }
+      }
+      __syncthreads();
+      for (int q = tid; q < n * ncol; q += nthr) {
+        const int i = q / ncol, c = q - (q / ncol) * ncol;
+        U[(int64_t)i * ldu + cb + c] = zs[c * n + i];
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
-  for (int64_t q = tid; q < (int64_t)n * nvec; q += nthr) U[(q / nvec) * ldu + q % nvec] = Z[q];
 }
 
 void symeig(const double* T, int ldt, int n, int nvec, double* theta, double* U, int ldu, EigWork& w, bool orth,
             hipStream_t st) {
   TRBL_REQUIRE(n >= 1 && n <= EIG_NMAX && nvec >= 1 && nvec <= n, TRBL_E_INVALID, "eigensolver size out of range");
-  (void)orth;
   w.a.alloc((size_t)n * n * sizeof(double));
   w.z.alloc((size_t)n * nvec * sizeof(double));
   w.lu.alloc((size_t)std::max(5 * n * nvec, nvec * nvec) * sizeof(double));
-  hipLaunchKernelGGL(symeig_kernel, dim3(1), dim3(EIG_THREADS), 0, st, T, ldt, n, nvec, theta, U, ldu, w.a.as<double>(),
-                     w.z.as<double>(), w.lu.as<double>());
+  hipLaunchKernelGGL(symeig_kernel, dim3(1), dim3(EIG_THREADS), 0, st, T, ldt, n, nvec, orth ? 1 : 0, theta, U, ldu,
+                     w.a.as<double>(), w.z.as<double>(), w.lu.as<double>());
   TRBL_HIP(hipGetLastError());
 }
 

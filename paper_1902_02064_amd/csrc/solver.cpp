@@ -116,7 +116,9 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
   double hnorm = 0.0;
   std::vector<double> th(neig), rh(neig);
   double t_hv = 0, t_orth = 0, t_qr = 0, t_eig = 0, t_rst = 0;
-  bool converged = false;
+  bool converged = false, last_orth = false;
+  int next_check = 1, it_prev = 0;  // adaptive convergence-test schedule (check_every < 0)
+  double r_prev = -1.0;
   int nchk = 0;
   for (it = 1; it <= o.max_iter; it++) {
     k++;
@@ -149,8 +151,8 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
     TRBL_HIP(hipEventRecord(ev.e[3], st));
     // diagonalise T^(k) (every check_every iterations and before every restart)
     const bool restart_next = mcur + 2 * nb > lm;
-    const int every = std::max(1, o.check_every);
-    if (!restart_next && it % every != 0 && it < o.max_iter) {
+    const bool check_now = o.check_every < 0 ? it >= next_check : it % std::max(1, o.check_every) == 0;
+    if (!restart_next && !check_now && it < o.max_iter) {
       TRBL_HIP(hipMemcpyAsync(sth, status, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
       TRBL_HIP(hipStreamSynchronize(st));
       t_hv += ev.ms(0, 1);
@@ -161,7 +163,8 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
       continue;
     }
     const int nvec = restart_next ? ls : std::min(neig, mcur);
-    symeig(T, lm, mcur, nvec, theta, U, ldu, ew, restart_next, st);
+    symeig(T, lm, mcur, nvec, theta, U, ldu, ew, restart_next, st);  // orthonormal U only where kept
+    last_orth = restart_next;
     nchk = std::min(neig, mcur);
     resid(beta, nb, U, ldu, mcur, nchk, rho, st);
     TRBL_HIP(hipEventRecord(ev.e[4], st));
@@ -194,6 +197,20 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
       converged = true;
       break;
     }
+    if (o.check_every < 0) {
+      // adaptive schedule: extrapolate the decay of the worst residual ratio r = rho / (tol |H|)
+      // seen since the previous test; test again a little before it is predicted to reach 1
+      double r = nchk < neig ? 1e30 : 0.0;
+      for (int i = 0; i < nchk; i++) r = std::max(r, rh[i] / (tol * hnorm));
+      int gap = r <= 1e2 ? 1 : 1 << 30;  // no usable rate: every iteration when close, else at restarts
+      if (r_prev > 0.0 && it > it_prev && r < r_prev) {
+        const double rate = std::log(r_prev / r) / (it - it_prev);
+        gap = std::max(1, (int)std::min(1e9, std::floor(0.75 * std::log(r) / rate)));
+      }
+      next_check = it + gap;
+      r_prev = r;
+      it_prev = it;
+    }
     if (restart_next && it < o.max_iter) {
       TRBL_HIP(hipEventRecord(ev.e[4], st));
       rowgemm<TQ, TQ>(Q, ldq, mcur, U, ldu, ls, Q, ldq, D, mcur, ls, nb, st);
@@ -213,6 +230,8 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
   std::vector<double> res(rh.begin(), rh.begin() + nchk);
   for (int i = 0; i < neig; i++) evals[i] = i < nchk ? th[i] : NAN;
   if (!mixed || !o.refine) {
+    // the convergence test may have used eigenvectors of T that were only normalised
+    if (evecs && !last_orth) symeig(T, lm, mcur, std::min(neig, mcur), theta, U, ldu, ew, true, st);
     if (evecs) rowgemm<TQ, double>(Q, ldq, mcur, U, ldu, neig, static_cast<double*>(evecs), neig, D, -1, 0, 0, st);
   } else {
     // FP64 Rayleigh-Ritz on span(X), X = Q U[:, :n_eig] stored in place in Q's first n_eig columns
