@@ -137,6 +137,7 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __re
 }
 
 // ------------------------------------------------------------------ Bout = Bin - A C (+ fused partial product)
+// (Bin == nullptr: Bout = A C.)
 // mode 0: update only; mode 1: also part[g] += A^T Bout (m x nb); mode 2: also part[g] += Bout^T Bout (nb x nb).
 // C (m x nb, FP64) is staged in LDS, padded to 16-multiples with zeros.
 template <class TA, class TI, int WAVES, int MAXI, int MAXC>
@@ -157,11 +158,14 @@ __global__ __launch_bounds__(WAVES * 64) void update_kernel(const TA* __restrict
   }
   __syncthreads();
   const int li = lane & 15, lk = lane >> 4;
-  d4 pacc[MAXI][MAXC];
+  const int npan = (m + 63) >> 6;  // 64-column panels of A (mode 1: panel p belongs to wave p % WAVES)
+  d4 pacc[MAXI][4][MAXC];          // mode 1: [panel slot][t][column tile]; mode 2: [0][qi][qj]
 #pragma unroll
   for (int i = 0; i < MAXI; i++)
 #pragma unroll
-    for (int q = 0; q < MAXC; q++) pacc[i][q] = d4{0, 0, 0, 0};
+    for (int t = 0; t < 4; t++)
+#pragma unroll
+      for (int q = 0; q < MAXC; q++) pacc[i][t][q] = d4{0, 0, 0, 0};
   const int64_t ntiles = (D + ROWS - 1) / ROWS;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t rbase = tile * ROWS;
@@ -193,7 +197,7 @@ __global__ __launch_bounds__(WAVES * 64) void update_kernel(const TA* __restrict
         const int c = q * 16 + li;
         double val = 0.0;
         if (r < D && c < nb) {
-          val = ld(Bin + r * ldi + c) - acc[q][v];
+          val = Bin ? ld(Bin + r * ldi + c) - acc[q][v] : acc[q][v];
           Bout[r * ldo + c] = val;
         }
         Wt[rl * nbp + c] = val;
@@ -203,6 +207,8 @@ __global__ __launch_bounds__(WAVES * 64) void update_kernel(const TA* __restrict
     __syncthreads();
     // ---- phase 2: fused partial product over the ROWS rows of this tile
     if (mode == 1) {
+      // A^T Bout over the tile's rows: lane loads 4 consecutive columns of a row of its wave's
+      // panel (32 bytes); value t feeds MFMA t (output row i stands for column 64 p + 4 i + t)
       for (int s = 0; s < ROWS / 4; s++) {
         const int rl = 4 * s + lk;
         const int64_t r = rbase + rl;
@@ -210,14 +216,18 @@ __global__ __launch_bounds__(WAVES * 64) void update_kernel(const TA* __restrict
 #pragma unroll
         for (int q = 0; q < MAXC; q++) bop[q] = (q < ct) ? Wt[rl * nbp + q * 16 + li] : 0.0;
 #pragma unroll
-        for (int ti = 0; ti < MAXI; ti++) {
-          const int it = wave + ti * WAVES;
-          if (it < mt) {
-            const int i = it * 16 + li;
-            const double aop = (r < D && i < m) ? ld(A + r * lda + i) : 0.0;
+        for (int pi = 0; pi < MAXI; pi++) {
+          const int pnl = wave + pi * WAVES;
+          const int c0 = 64 * pnl + 4 * li;
+          if (pnl < npan) {
+            double a4[4];
+            if (r < D && c0 < m) ld4(A + r * lda + c0, m - c0, a4);
+            else a4[0] = a4[1] = a4[2] = a4[3] = 0.0;
 #pragma unroll
-            for (int q = 0; q < MAXC; q++)
-              if (q < ct) pacc[ti][q] = mfma(aop, bop[q], pacc[ti][q]);
+            for (int t = 0; t < 4; t++)
+#pragma unroll
+              for (int q = 0; q < MAXC; q++)
+                if (q < ct) pacc[pi][t][q] = mfma(a4[t], bop[q], pacc[pi][t][q]);
           }
         }
       }
@@ -231,7 +241,7 @@ __global__ __launch_bounds__(WAVES * 64) void update_kernel(const TA* __restrict
           const double aop = Wt[rl * nbp + qi * 16 + li];
 #pragma unroll
           for (int qj = 0; qj < MAXC; qj++)
-            if (qj < ct) pacc[qi][qj] = mfma(aop, Wt[rl * nbp + qj * 16 + li], pacc[qi][qj]);
+            if (qj < ct) pacc[0][qi][qj] = mfma(aop, Wt[rl * nbp + qj * 16 + li], pacc[0][qi][qj]);
         }
       }
     }
@@ -241,18 +251,20 @@ __global__ __launch_bounds__(WAVES * 64) void update_kernel(const TA* __restrict
   double* out = part + (int64_t)blockIdx.x * (mode == 1 ? (int64_t)m * nb : (int64_t)nb * nb);
   if (mode == 1) {
 #pragma unroll
-    for (int ti = 0; ti < MAXI; ti++) {
-      const int it = wave + ti * WAVES;
-      if (it >= mt) continue;
+    for (int pi = 0; pi < MAXI; pi++) {
+      const int pnl = wave + pi * WAVES;
+      if (pnl >= npan) continue;
 #pragma unroll
-      for (int q = 0; q < MAXC; q++) {
-        if (q >= ct) continue;
+      for (int t = 0; t < 4; t++)
 #pragma unroll
-        for (int v = 0; v < 4; v++) {
-          const int i = it * 16 + lk + 4 * v, c = q * 16 + li;
-          if (i < m && c < nb) out[i * nb + c] = pacc[ti][q][v];
+        for (int q = 0; q < MAXC; q++) {
+          if (q >= ct) continue;
+#pragma unroll
+          for (int v = 0; v < 4; v++) {
+            const int i = 64 * pnl + 4 * (lk + 4 * v) + t, c = q * 16 + li;
+            if (i < m && c < nb) out[i * nb + c] = pacc[pi][t][q][v];
+          }
         }
-      }
     }
   } else {
     // reduce the per-wave Gram tiles through LDS, one wave after the other
@@ -269,7 +281,7 @@ __global__ __launch_bounds__(WAVES * 64) void update_kernel(const TA* __restrict
         for (int qj = 0; qj < MAXC; qj++) {
           if (qj >= ct) continue;
 #pragma unroll
-          for (int v = 0; v < 4; v++) red[(qi * 16 + lk + 4 * v) * nbp + qj * 16 + li] += pacc[qi][qj][v];
+          for (int v = 0; v < 4; v++) red[(qi * 16 + lk + 4 * v) * nbp + qj * 16 + li] += pacc[0][qi][qj][v];
         }
       }
     }
@@ -587,37 +599,36 @@ void tn(const TA* A, int64_t lda, int m, const TB* B, int64_t ldb, int nb, int64
 template <class TA, class TI>
 void update(const TA* A, int64_t lda, int m, const double* C, const TI* Bin, int64_t ldi, double* Bout, int64_t ldo,
             int nb, int64_t D, int mode, double* Pout, Scratch& s, hipStream_t st) {
-  TRBL_REQUIRE(m <= 768 && nb <= 64, TRBL_E_INVALID, "projection too wide");
-  const int mt = (m + 15) / 16, ct = (nb + 15) / 16;
+  TRBL_REQUIRE(m >= 1 && m <= 768 && nb >= 1 && nb <= 64, TRBL_E_INVALID, "projection shape out of range");
+  const int mt = (m + 15) / 16, ct = (nb + 15) / 16, npan = (m + 63) / 64;
   auto shm_for = [&](int waves) {
     size_t b = (size_t)(mt * 16 * ct * 16 + waves * 16 * ct * 16) * sizeof(double);
     return std::max(b, (size_t)ct * 16 * ct * 16 * sizeof(double));
   };
-  const int waves = (shm_for(8) <= 160 * 1024 && mt <= 48) ? 8 : 4;
+  const int waves = (shm_for(8) <= 160 * 1024) ? 8 : 4;
   const size_t shm = shm_for(waves);
-  TRBL_REQUIRE(shm <= 160 * 1024 && (mt + waves - 1) / waves <= (waves == 8 ? 6 : 12), TRBL_E_INVALID,
-               "update tile does not fit in LDS");
+  TRBL_REQUIRE(shm <= 160 * 1024, TRBL_E_INVALID, "update tile does not fit in LDS");
   int G = grid_for(D, waves * 16 * 4, 1024);
   const int64_t plen = mode == 1 ? (int64_t)m * nb : (int64_t)nb * nb;
   double* part = mode ? s.partials((size_t)G * plen) : nullptr;
-  const int mi = (mt + waves - 1) / waves;
+  const int mi = (npan + waves - 1) / waves;  // 64-column panels per wave (mode 1)
 #define UPD_LAUNCH(W, MI, MC)                                                                                     \
   hipLaunchKernelGGL((update_kernel<TA, TI, W, MI, MC>), dim3(G), dim3(W * 64), shm, st, A, lda, m, C, Bin, ldi, \
                      Bout, ldo, nb, D, mode, part)
   if (waves == 8) {
     if (ct == 1) {
-      if (mi <= 2) UPD_LAUNCH(8, 2, 1);
-      else if (mi <= 4) UPD_LAUNCH(8, 4, 1);
-      else UPD_LAUNCH(8, 6, 1);
+      if (mi <= 1) UPD_LAUNCH(8, 1, 1);
+      else UPD_LAUNCH(8, 2, 1);
     } else if (ct == 2) {
-      if (mi <= 3) UPD_LAUNCH(8, 3, 2);
-      else UPD_LAUNCH(8, 6, 2);
+      if (mi <= 1) UPD_LAUNCH(8, 1, 2);
+      else UPD_LAUNCH(8, 2, 2);
     } else {
-      UPD_LAUNCH(8, 6, 4);
+      if (mi <= 1) UPD_LAUNCH(8, 1, 4);
+      else UPD_LAUNCH(8, 2, 4);
     }
   } else {
-    if (ct <= 2) UPD_LAUNCH(4, 12, 2);
-    else UPD_LAUNCH(4, 12, 4);
+    if (ct <= 2) UPD_LAUNCH(4, 3, 2);
+    else UPD_LAUNCH(4, 3, 4);
   }
 #undef UPD_LAUNCH
   if (mode) {
@@ -633,6 +644,10 @@ void update(const TA* A, int64_t lda, int m, const double* C, const TI* Bin, int
 template <class TI, class TO>
 void apply_small(const TI* Bin, int64_t ldi, const double* R, TO* Bout, int64_t ldo, int nb, int64_t D, bool gram,
                  Scratch& s, hipStream_t st) {
+  if constexpr (sizeof(TO) == 8) {  // FP64 output: the MFMA row-streaming kernel, Bout = Bin R (+ Gram)
+    update<TI, TI>(Bin, ldi, nb, R, nullptr, 0, Bout, ldo, nb, D, gram ? 2 : 0, nullptr, s, st);
+    return;
+  }
   const int rows = 2048 / nb;
   const int G = grid_for(D, rows * 4, 1024);
   double* part = gram ? s.partials((size_t)G * nb * nb) : nullptr;
