@@ -56,11 +56,22 @@ def stored_nnz(name):
     return None
 
 
+HV_SOURCES = ("hv.hip", "hv_kern.h", "hv_f64.hip", "hv_f32.hip")
+
+
+def hv_source_digest():
+    """Digest of the block H.V sources (a stored counter summary is valid only for these)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in HV_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1902_02064_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def stored_traffic(name):
     """Measured HBM bytes per H.V launch from the committed counter summary, if it matches the source."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"hv_{name}_traffic.txt")
-    src = os.path.join(ROOT, "paper_1902_02064_amd", "csrc", "hv.hip")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -68,7 +79,7 @@ def stored_traffic(name):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    digest = hv_source_digest()
     if kv.get("hv_source_sha256_16") != digest:
         return None
     return float(kv["fp64_bytes_per_launch"])

@@ -39,22 +39,50 @@ def fix_signs(X):
     return X
 
 
-def trbl(apply, dim, V1, n_eig, l_s, l_m, tol, max_iter=10000, seed=12345, history=None):
+def _save_state(path, Q, T, kx, k, hnorm, it, info, rng):
+    """Resumable state after a restart (long runs only; no arithmetic here)."""
+    import json
+    import os
+    np.save(os.path.join(path, "Q.npy.tmp.npy"), Q)
+    np.save(os.path.join(path, "T.npy.tmp.npy"), T)
+    os.replace(os.path.join(path, "Q.npy.tmp.npy"), os.path.join(path, "Q.npy"))
+    os.replace(os.path.join(path, "T.npy.tmp.npy"), os.path.join(path, "T.npy"))
+    meta = {"kx": kx, "k": k, "hnorm": hnorm, "it": it, "info": info, "rng": rng.bit_generator.state}
+    with open(os.path.join(path, "meta.json.tmp"), "w") as f:
+        json.dump(meta, f)
+    os.replace(os.path.join(path, "meta.json.tmp"), os.path.join(path, "meta.json"))
+
+
+def trbl(apply, dim, V1, n_eig, l_s, l_m, tol, max_iter=10000, seed=12345, history=None, checkpoint=None):
     """Lowest ``n_eig`` eigenpairs of the symmetric operator ``apply`` (D x p -> D x p).
 
     V1: D x p start block (orthonormalised here). Returns (evals, evecs, info).
+    checkpoint: optional directory; the state is saved after every restart and a run
+    started with a saved state there continues from it (same iterates).
     """
+    import json
+    import os
     p = V1.shape[1]
     if not (n_eig <= l_s and l_s + 2 * p <= l_m and l_m <= dim):
         raise ValueError("need n_eig <= l_s, l_s + 2p <= l_m <= D")
     rng = np.random.default_rng(seed)
-    Q = np.zeros((dim, l_m))
-    T = np.zeros((l_m, l_m))
-    Q[:, :p], _ = _qr_pos(np.asarray(V1, dtype=np.float64))
-    kx, k = 0, 0
-    hnorm = 0.0
-    info = {"iterations": 0, "restarts": 0, "converged": False}
-    for it in range(1, max_iter + 1):
+    it0 = 1
+    if checkpoint and os.path.exists(os.path.join(checkpoint, "meta.json")):
+        with open(os.path.join(checkpoint, "meta.json")) as f:
+            meta = json.load(f)
+        Q = np.load(os.path.join(checkpoint, "Q.npy"))
+        T = np.load(os.path.join(checkpoint, "T.npy"))
+        kx, k, hnorm, info = meta["kx"], meta["k"], meta["hnorm"], meta["info"]
+        rng.bit_generator.state = meta["rng"]
+        it0 = meta["it"] + 1
+    else:
+        Q = np.zeros((dim, l_m))
+        T = np.zeros((l_m, l_m))
+        Q[:, :p], _ = _qr_pos(np.asarray(V1, dtype=np.float64))
+        kx, k = 0, 0
+        hnorm = 0.0
+        info = {"iterations": 0, "restarts": 0, "converged": False}
+    for it in range(it0, max_iter + 1):
         k += 1
         c0 = kx + (k - 1) * p
         m = c0 + p
@@ -103,6 +131,8 @@ def trbl(apply, dim, V1, n_eig, l_s, l_m, tol, max_iter=10000, seed=12345, histo
             T[:l_s, l_s:l_s + p] = r.T
             kx, k = l_s, 0
             info["restarts"] += 1
+            if checkpoint:
+                _save_state(checkpoint, Q, T, kx, k, hnorm, it, info, rng)
     info["resid"] = rho
     X = Q[:, :m] @ U[:, :n_eig]
     return theta[:n_eig], X, info

@@ -1,6 +1,7 @@
 // Block H.V planning and launch (App. B), and device-side basis indexing (App. A).
 // The H.V kernels themselves are in hv_kern.h, instantiated per precision in
 // hv_f64.hip and hv_f32.hip.
+#include <cstdlib>
 #include <map>
 
 #include "hv_kern.h"
@@ -18,7 +19,8 @@ static int pow2ceil(int x) {
 
 static int rs_of(int C, size_t elt) { return elt == 8 ? (C >= 2 ? C + 2 : 2) : (C >= 4 ? C + 4 : 4); }
 
-constexpr size_t ROW_SMALL = 24 * 1024, ROW_LARGE = 72 * 1024;  // LDS bytes per row buffer (rows kernel)
+// LDS bytes per row buffer of the rows kernel: 24 KB and 36 KB leave room for two workgroups per CU
+constexpr size_t ROW_SMALL = 24 * 1024, ROW_MID = 36 * 1024, ROW_LARGE = 72 * 1024;
 
 static HVPlan& plan_for(const Model& m, int nb, size_t elt) {
   const int key = nb * 16 + (int)elt;
@@ -29,6 +31,10 @@ static HVPlan& plan_for(const Model& m, int nb, size_t elt) {
   // 1024-wide workgroups leave 128 VGPRs per lane: narrower tiles there
   const int cmin = (int)(16 / elt), cmax = (elt == 8 ? 16 : 32) / (m.max_dn > 768 ? 2 : 1);
   int C = std::max(cmin, std::min(cmax, pow2ceil(nb)));
+  if (const char* env = std::getenv("TRBL_HV_TILE")) {  // tuning override: a narrower power-of-two tile
+    C = std::max(cmin, std::min(C, std::atoi(env)));
+    while (C & (C - 1)) C &= C - 1;
+  }
   while (C > cmin && (size_t)m.max_dn * C * elt > ROW_LARGE) C >>= 1;
   TRBL_REQUIRE((size_t)m.max_dn * C * elt <= ROW_LARGE, TRBL_E_INVALID, "neutron sector too large for the LDS row tile");
   TRBL_REQUIRE((size_t)m.max_dp * rs_of(C, elt) * elt <= 144 * 1024, TRBL_E_INVALID,
@@ -49,7 +55,8 @@ static HVPlan& plan_for(const Model& m, int nb, size_t elt) {
     }
     const int nthr = std::min(1024, (dn + 63) / 64 * 64);
     const int ntb = nthr <= 256 ? 256 : nthr <= 768 ? 768 : 1024;
-    const int rb = (size_t)widest * C * elt <= ROW_SMALL ? 24 : 72;
+    const size_t need = (size_t)widest * C * elt;
+    const int rb = need <= ROW_SMALL ? 24 : need <= ROW_MID ? 36 : 72;
     members[{ntb, rb}].push_back((int)b);
   }
   for (auto& kv : members) {

@@ -207,7 +207,9 @@ __device__ __forceinline__ GroupIt next_group(const HVArgs<T>& a, int b, int gp,
 }
 
 constexpr int MAXE = 8;           // neutron jumps per (target, class) kept in registers
-constexpr int HS_BYTES = 8192;    // LDS rows of the class table used by the target's proton jumps
+// LDS rows of the class table used by the target's proton jumps (smaller with the 36 KB row
+// buffers, so that two workgroups fit in the 160 KB of LDS of a CU)
+constexpr int hs_bytes(int rbkb) { return rbkb == 36 ? 4096 : 8192; }
 
 // Rows kernel: neutron-neutron and proton-neutron parts of W for one proton row p' of one
 // block (App. B). One lane owns target n' (sectors wider than 1024 are split in chunks) and the C
@@ -217,7 +219,7 @@ template <class T, int C, int NTB, int RBKB, bool DMA>
 __global__ __launch_bounds__(NTB) void hv_rows_kernel(HVArgs<T> a) {
   constexpr int MAXP = 1;  // targets per lane (wider sectors are split into chunks)
   constexpr int RBYTES = RBKB * 1024;
-  constexpr int HSN = HS_BYTES / (int)sizeof(T);
+  constexpr int HSN = hs_bytes(RBKB) / (int)sizeof(T);
   __shared__ __align__(16) char B0[RBYTES];
   __shared__ __align__(16) char B1[RBYTES];
   __shared__ __align__(16) T HS[HSN];
@@ -435,10 +437,13 @@ static void dispatch_c(HVArgs<T>& a, const HVPlan& P, hipStream_t s) {
     a.bin_blocks = B.blocks.as<int>();
     a.bin_item0 = B.item0.as<int64_t>();
     a.bin_nblk = B.nblk;
-    const bool small = B.rb_kb <= 24;
-    if (B.ntb == 256) small ? launch_rows<T, C, 256, 24>(a, B, s) : launch_rows<T, C, 256, 72>(a, B, s);
-    else if (B.ntb == 768) small ? launch_rows<T, C, 768, 24>(a, B, s) : launch_rows<T, C, 768, 72>(a, B, s);
-    else small ? launch_rows<T, C, 1024, 24>(a, B, s) : launch_rows<T, C, 1024, 72>(a, B, s);
+#define TRBL_ROWS_RB(NTB)                                                   \
+  (B.rb_kb == 24 ? launch_rows<T, C, NTB, 24>(a, B, s)                      \
+                 : B.rb_kb == 36 ? launch_rows<T, C, NTB, 36>(a, B, s) : launch_rows<T, C, NTB, 72>(a, B, s))
+    if (B.ntb == 256) TRBL_ROWS_RB(256);
+    else if (B.ntb == 768) TRBL_ROWS_RB(768);
+    else TRBL_ROWS_RB(1024);
+#undef TRBL_ROWS_RB
   }
   a.nchunk = P.nchunk_c;
   if (P.maxp_c == 1) launch_cols<T, C, 1>(a, P, s);

@@ -43,7 +43,11 @@ def run(wname):
     V1 = random_block(1000, m.dim, w.nb)
     tol = min(w.tol, 1e-10)
     hist = []
-    ev, X, info = trbl(m.apply, m.dim, V1, w.n_eig, w.l_s, w.l_m, tol, history=hist)
+    ckpt = os.environ.get("TRBL_GOLDEN_CKPT")  # optional directory: resumable long runs
+    if ckpt:
+        ckpt = os.path.join(ckpt, wname)
+        os.makedirs(ckpt, exist_ok=True)
+    ev, X, info = trbl(m.apply, m.dim, V1, w.n_eig, w.l_s, w.l_m, tol, history=hist, checkpoint=ckpt)
     print(wname, "iterations", info["iterations"], "restarts", info["restarts"], "converged", info["converged"],
           "%.0f s" % (time.time() - t0), flush=True)
     write(f"{wname}_eigs.txt",

@@ -93,3 +93,15 @@ def test_gradient_fd_and_euler(sd22):
         em = np.linalg.eigvalsh(m.with_interaction([tuple(x) for x in tm], w.spe, w.spe).dense())[:n]
         fd = (wt @ ep - wt @ em) / (2 * h)
         assert abs(fd - g[i]) <= 1e-5 * max(abs(g[i]), 1e-3 * np.max(np.abs(g)))
+
+
+def test_trbl_checkpoint_resume(sd22, tmp_path):
+    """A run stopped after some restarts and resumed from its checkpoint takes the same iterates."""
+    w, o = sd22[0], sd22[1]
+    V1 = random_block(1000, o.dim, w.nb)
+    ev_ref, _, info_ref = trbl(o.apply, o.dim, V1, w.n_eig, w.l_s, w.l_m, 1e-10)
+    assert info_ref["restarts"] >= 2
+    trbl(o.apply, o.dim, V1, w.n_eig, w.l_s, w.l_m, 1e-10, max_iter=25, checkpoint=str(tmp_path))
+    ev, _, info = trbl(o.apply, o.dim, V1, w.n_eig, w.l_s, w.l_m, 1e-10, checkpoint=str(tmp_path))
+    assert info["iterations"] == info_ref["iterations"]
+    assert np.array_equal(ev, ev_ref)
