@@ -96,6 +96,70 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
   EigWork ew;
   Events ev;
 
+  // Column-by-column QR with replacement, for a block that Cholesky QR finds rank deficient
+  // (breakdown / Krylov exhaustion): X = Wsrc (D x nb, FP64) is orthogonalised twice against
+  // Q[:, :mprev] and the earlier new columns; a column whose remaining norm is <= 1e-10 of the
+  // largest column norm is replaced by a random vector orthogonal to all of them, with a zero
+  // diagonal entry of beta. Writes Q[:, mprev:mprev+nb] and beta (upper, W = V_new beta).
+  int breakdowns = 0;
+  DevBuf xb, cb, nrmb, rib;
+  auto robust_qr = [&](const double* Wsrc, int mprev, uint64_t salt) {
+    xb.alloc((size_t)D * sizeof(double));
+    cb.alloc((size_t)(lm + nb) * sizeof(double));
+    nrmb.alloc(sizeof(double));
+    rib.alloc(sizeof(double));
+    double* x = xb.as<double>();
+    double* cdev = cb.as<double>();
+    std::vector<double> bh((size_t)nb * nb, 0.0), ch(lm + nb);
+    auto dot_xx = [&]() {
+      double h;
+      tn<double, double>(x, 1, 1, x, 1, 1, D, nrmb.as<double>(), sc, st);
+      TRBL_HIP(hipMemcpyAsync(&h, nrmb.p, sizeof(double), hipMemcpyDeviceToHost, st));
+      TRBL_HIP(hipStreamSynchronize(st));
+      return std::sqrt(std::max(h, 0.0));
+    };
+    auto orth_against = [&](int mo, double* coef) {  // x -= Q[:, :mo] (Q[:, :mo]^T x), twice
+      for (int pass = 0; pass < 2 && mo > 0; pass++) {
+        tn<TQ, double>(Q, ldq, mo, x, 1, 1, D, cdev, sc, st);
+        update<TQ, double>(Q, ldq, mo, cdev, x, 1, x, 1, 1, D, 0, nullptr, sc, st);
+        if (coef) {
+          TRBL_HIP(hipMemcpyAsync(ch.data(), cdev, mo * sizeof(double), hipMemcpyDeviceToHost, st));
+          TRBL_HIP(hipStreamSynchronize(st));
+          for (int i = 0; i < mo; i++) coef[i] += ch[i];
+        }
+      }
+    };
+    double wmax = 0.0;
+    std::vector<double> wn(nb);
+    for (int j = 0; j < nb; j++) {
+      copy_cols<double, double>(Wsrc + j, nb, x, 1, D, 1, st);
+      wn[j] = dot_xx();
+      wmax = std::max(wmax, wn[j]);
+    }
+    for (int j = 0; j < nb; j++) {
+      copy_cols<double, double>(Wsrc + j, nb, x, 1, D, 1, st);
+      std::vector<double> coef(mprev + j, 0.0);
+      orth_against(mprev + j, coef.data());
+      for (int i = 0; i < j; i++) bh[(size_t)i * nb + j] = coef[mprev + i];
+      double nr = dot_xx();
+      if (!(nr > 1e-10 * wmax) || !(wmax > 0.0)) {
+        random_block<double>(x, 1, D, 1, o.seed ^ (0x9E3779B97F4A7C15ull * (salt + 1 + j)), st);
+        orth_against(mprev + j, nullptr);
+        nr = dot_xx();
+        TRBL_REQUIRE(nr > 0.0, TRBL_E_BREAKDOWN, "no vector left outside the Krylov basis");
+        bh[(size_t)j * nb + j] = 0.0;
+        breakdowns++;
+      } else {
+        bh[(size_t)j * nb + j] = nr;
+      }
+      const double inv = 1.0 / nr;
+      TRBL_HIP(hipMemcpyAsync(rib.p, &inv, sizeof(double), hipMemcpyHostToDevice, st));
+      apply_small<double, TQ>(x, 1, rib.as<double>(), Q + mprev + j, ldq, 1, D, false, sc, st);
+    }
+    TRBL_HIP(hipMemcpyAsync(beta, bh.data(), bh.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    TRBL_HIP(hipStreamSynchronize(st));
+  };
+
   // ---- start block V_1 (orthonormalised by Cholesky QR twice)
   if (o.v0)
     copy_cols<TQ, TQ>(static_cast<const TQ*>(o.v0), nb, Q, ldq, D, nb, st);
@@ -110,7 +174,14 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
   int sth[4] = {0, 0, 0, 0};
   TRBL_HIP(hipMemcpyAsync(sth, status, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
   TRBL_HIP(hipStreamSynchronize(st));
-  TRBL_REQUIRE(sth[0] == 0 && sth[1] == 0, TRBL_E_BREAKDOWN, "start block is rank deficient");
+  if (sth[0] || sth[1]) {  // rank-deficient start block: column-wise QR with replacement
+    if (o.v0) copy_cols<TQ, double>(static_cast<const TQ*>(o.v0), nb, W, nb, D, nb, st);
+    else {
+      random_block<TQ>(Q, ldq, D, nb, o.seed, st);
+      copy_cols<TQ, double>(Q, ldq, W, nb, D, nb, st);
+    }
+    robust_qr(W, 0, 0);
+  }
 
   int kx = 0, k = 0, it = 0, restarts = 0, mcur = 0;
   double hnorm = 0.0;
@@ -148,18 +219,34 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
     chol(sc.last_part, sc.last_G, nb, R2, R2i, R1, beta, status + 1, st);
     apply_small<double, TQ>(W, nb, R2i, Q + mcur, ldq, nb, D, false, sc, st);
     t_beta(T, lm, c0, mcur, nb, beta, st);
+    TRBL_HIP(hipMemcpyAsync(sth, status, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    TRBL_HIP(hipStreamSynchronize(st));
+    if (sth[0] || sth[1]) {
+      // breakdown: W was scaled in place; form it again (same arithmetic) and take the
+      // column-wise QR with replacement
+      launch_apply(m, mixed ? TRBL_MIXED : TRBL_FP64, nb, Q + c0, ldq, Wh, nb, st);
+      if (mixed) {
+        tn<float, float>((const float*)Q, ldq, mcur, W32, nb, nb, D, C1, sc, st);
+        update<float, float>((const float*)Q, ldq, mcur, C1, W32, nb, W, nb, nb, D, 1, C2, sc, st);
+        update<float, double>((const float*)Q, ldq, mcur, C2, W, nb, W, nb, nb, D, 0, nullptr, sc, st);
+      } else {
+        tn<double, double>((const double*)Q, ldq, mcur, W, nb, nb, D, C1, sc, st);
+        update<double, double>((const double*)Q, ldq, mcur, C1, W, nb, W, nb, nb, D, 1, C2, sc, st);
+        update<double, double>((const double*)Q, ldq, mcur, C2, W, nb, W, nb, nb, D, 0, nullptr, sc, st);
+      }
+      robust_qr(W, mcur, (uint64_t)it);
+      t_beta(T, lm, c0, mcur, nb, beta, st);
+      sth[0] = sth[1] = 0;
+    }
     TRBL_HIP(hipEventRecord(ev.e[3], st));
     // diagonalise T^(k) (every check_every iterations and before every restart)
     const bool restart_next = mcur + 2 * nb > lm;
     const bool check_now = o.check_every < 0 ? it >= next_check : it % std::max(1, o.check_every) == 0;
     if (!restart_next && !check_now && it < o.max_iter) {
-      TRBL_HIP(hipMemcpyAsync(sth, status, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-      TRBL_HIP(hipStreamSynchronize(st));
+      TRBL_HIP(hipEventSynchronize(ev.e[3]));
       t_hv += ev.ms(0, 1);
       t_orth += ev.ms(1, 2);
       t_qr += ev.ms(2, 3);
-      TRBL_REQUIRE(sth[0] == 0 && sth[1] == 0, TRBL_E_BREAKDOWN,
-                   "block Lanczos breakdown: new block is numerically rank deficient");
       continue;
     }
     const int nvec = restart_next ? ls : std::min(neig, mcur);
@@ -172,14 +259,11 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
     double tmax = 0.0;
     TRBL_HIP(hipMemcpyAsync(&tmax, theta + mcur - 1, sizeof(double), hipMemcpyDeviceToHost, st));
     TRBL_HIP(hipMemcpyAsync(rh.data(), rho, nchk * sizeof(double), hipMemcpyDeviceToHost, st));
-    TRBL_HIP(hipMemcpyAsync(sth, status, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
     TRBL_HIP(hipStreamSynchronize(st));
     t_hv += ev.ms(0, 1);
     t_orth += ev.ms(1, 2);
     t_qr += ev.ms(2, 3);
     t_eig += ev.ms(3, 4);
-    TRBL_REQUIRE(sth[0] == 0 && sth[1] == 0, TRBL_E_BREAKDOWN,
-                 "block Lanczos breakdown: new block is numerically rank deficient");
     hnorm = std::max(hnorm, std::max(std::fabs(th[0]), std::fabs(tmax)));
     bool ok = nchk == neig;
     int nconv_it = 0;
@@ -292,7 +376,7 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
   if (info) {
     info->iterations = it;
     info->restarts = restarts;
-    info->breakdowns = 0;
+    info->breakdowns = breakdowns;
     int nconv = 0;
     for (int i = 0; i < nchk; i++) nconv += rh[i] <= tol * hnorm;
     info->n_converged = nconv;

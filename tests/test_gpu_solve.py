@@ -84,3 +84,37 @@ def test_degenerate_spectrum_block_finds_distinct_values():
     ev, _, info = g.solve(4, 4, 12, 40, 1e-10, "fp64")
     assert info.converged
     assert np.allclose(ev, -15.6, atol=1e-9)
+
+
+def test_breakdown_duplicated_start_block(sd22):
+    """Rank-deficient start block (duplicated columns): the column-wise QR replaces the deficient
+    columns by random vectors orthogonal to the basis, and the solve still converges."""
+    w, g, o, H, e = sd22
+    V = random_block(5, g.dim, 2)
+    V1 = np.concatenate([V, V], axis=1) + 1e-14
+    say("solve sd22 duplicated start block")
+    ev, _, info = g.solve(4, 8, 16, 48, 1e-9, "fp64", v0=torch.from_numpy(V1).cuda())
+    say("breakdowns", info.breakdowns, "iterations", info.iterations)
+    assert info.converged and info.breakdowns >= 1
+    assert np.abs(ev - e[:8]).max() <= 1e-9 * np.abs(e).max()
+
+
+def test_krylov_exhaustion_small_space():
+    """f7/2 with 2+2 nucleons: the block Krylov space fills the whole space; breakdowns are
+    handled and the lowest eigenvalues come out exactly."""
+    tb = [(0, 0, 0, 0, 0, 0, 0.5), (2, 0, 0, 0, 0, 4, -1.0)]
+    g, o = pair(((0, 3, 7),), 2, 2, 0, tb, (0.0,), (0.0,))
+    e = np.linalg.eigvalsh(o.dense())
+    ev, _, info = g.solve(2, 3, 4, min(g.dim, 12), 1e-10, "fp64")
+    say("tiny D", g.dim, "breakdowns", info.breakdowns, "ev", ev, "exact", e[:3])
+    assert info.converged
+    assert np.abs(ev - e[:3]).max() <= 1e-9 * max(1.0, np.abs(e).max())
+
+
+@pytest.mark.parametrize("every", [1, 3, -1])
+def test_check_schedules_agree(sd22, every):
+    """Convergence tested every iteration, every 3rd, or on the adaptive schedule: same eigenpairs."""
+    w, g, o, H, e = sd22
+    ev, _, info = g.solve(w.nb, w.n_eig, w.l_s, w.l_m, w.tol, "fp64", check_every=every)
+    assert info.converged
+    assert np.abs(ev - e[:w.n_eig]).max() <= 1e-8 * np.abs(e[:w.n_eig]).max()
