@@ -388,6 +388,18 @@ __global__ __launch_bounds__(EIG_THREADS) void symeig_kernel(const double* __res
             if (r0 + a < nvec && c0 + b < nvec && c0 + b >= r0 + a) G[(int64_t)(r0 + a) * nvec + c0 + b] = acc[a][b];
     }
     __syncthreads();
+    {  // already orthonormal to working accuracy (well separated eigenvalues): nothing to do
+      double off = 0.0;
+      for (int r = wave; r < nvec; r += nwave)
+        for (int c = r + lane; c < nvec; c += 64) off = fmax(off, fabs(G[(int64_t)r * nvec + c] - (r == c ? 1.0 : 0.0)));
+      for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_xor(off, o, 64));
+      if (lane == 0) red[wave] = off;
+      __syncthreads();
+      off = 0.0;
+      for (int w = 0; w < nwave; w++) off = fmax(off, red[w]);
+      __syncthreads();
+      if (off <= 64.0 * DBL_EPSILON) break;
+    }
     // upper Cholesky G = R^T R in place (row k finalised at step k)
     for (int k = 0; k < nvec; k++) {
       const double rkk = sqrt(fmax(G[(int64_t)k * nvec + k], 1e-300));
