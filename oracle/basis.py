@@ -106,6 +106,17 @@ class ProductBasis:
         ns = self.nstates
         return [pw | (nw << ns) for pw, nw in self.states()]
 
+    def combined_words_array(self):
+        """combined_words() as a uint64 array, built block by block (same order; for large spaces)."""
+        import numpy as np
+        ns = np.uint64(self.nstates)
+        out = np.empty(self.dim, dtype=np.uint64)
+        for b in self.blocks:
+            pw = np.array([w for w, _ in self.psec[(b.twoMp, b.parp)]], dtype=np.uint64)
+            nw = np.array([w for w, _ in self.nsec[(b.twoMn, b.parn)]], dtype=np.uint64)
+            out[b.offset:b.offset + b.dp * b.dn] = (pw[:, None] | (nw[None, :] << ns)).ravel()
+        return out
+
 
 def count_sds(orbits, n_part):
     """Number of SDs by (2M, parity) for ``n_part`` nucleons, by dynamic programming over orbits.

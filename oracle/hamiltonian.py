@@ -53,7 +53,7 @@ class Model:
         self.S = 2 * self.basis.nstates
         if self.S > 64:
             raise ValueError("oracle handles at most 64 combined single-particle states")
-        self.words = np.array(self.basis.combined_words(), dtype=np.uint64)
+        self.words = self.basis.combined_words_array()
         order = np.argsort(self.words, kind="stable")
         self.sorted = np.ascontiguousarray(self.words[order])
         self.sidx = np.ascontiguousarray(order.astype(np.int64))

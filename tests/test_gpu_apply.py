@@ -87,3 +87,33 @@ def test_apply_full_size_sampled_rows(wname, nrows):
         sl = slice(ptr[r], ptr[r + 1])
         absHV32[r] = np.abs(val[sl]) @ np.abs(V32[col[sl]].astype(np.float64))
     assert np.all(np.abs(W32[idx] - ref32) <= fp32_bound(absHV32, nnz))
+
+
+def test_apply_pf66_sampled_rows():
+    """pf shell 6+6 (D = 109,954,620; neutron sectors up to 3,952 SDs, so the rows kernel splits
+    targets into chunks and the column tile shrinks to fit LDS): 60 sampled rows against the oracle,
+    nb = 4 to keep the host-side input at 3.5 GB."""
+    w = WORKLOADS["pf66"]
+    say("case pf66 full size, nb=4")
+    g, o = pair(w.orbits, w.n_prot, w.n_neut, w.twoM, w.tbme(), w.spe, w.spe)
+    assert g.dim == o.dim == 109954620
+    V = random_block(2000, g.dim, 4)
+    rng = np.random.default_rng(5)
+    idx = np.unique(np.concatenate([rng.choice(g.dim, 60, replace=False), [0, g.dim - 1]]))
+    ref = o.apply_rows(V, idx)
+    ptr, col, val = o.rows(idx)
+    absHV = np.zeros_like(ref)
+    for r in range(len(idx)):
+        sl = slice(ptr[r], ptr[r + 1])
+        absHV[r] = np.abs(val[sl]) @ np.abs(V[col[sl]])
+    nnz = int(np.max(np.diff(ptr)))
+    Vd = torch.from_numpy(V).cuda()
+    W = g.apply(Vd)[torch.from_numpy(idx).cuda()].cpu().numpy()
+    say("pf66 fp64 max err", np.abs(W - ref).max())
+    assert np.all(np.abs(W - ref) <= fp64_bound(absHV, nnz))
+    del Vd
+    V32 = V.astype(np.float32)
+    del V
+    W32 = g.apply(torch.from_numpy(V32).cuda())[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.float64)
+    ref32 = o.apply_rows(V32.astype(np.float64), idx)
+    assert np.all(np.abs(W32 - ref32) <= fp32_bound(absHV * 1.0001, nnz))

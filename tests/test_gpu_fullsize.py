@@ -73,3 +73,19 @@ def test_pf44_mixed_vs_fp64(pf44):
     rel = np.abs(evm - ev) / np.abs(ev)
     say("pf44 mixed max rel err", rel.max(), "median", np.median(rel), im.iterations, "iterations")
     assert rel.max() <= 1e-6
+
+
+def test_pf66_mixed_iterations_fit_and_descend():
+    """pf shell 6+6 (D = 109,954,620), mixed precision, nb = 32, 200 wanted, l_s = 384, l_m = 448:
+    the FP32 basis (197 GB) fits one GPU next to the FP64 work block. A full solve is beyond a test's
+    time; two and four iterations from the same start: the lowest Ritz value can only go down
+    (the Krylov space grows, no restart yet) and every Ritz value stays finite."""
+    w = WORKLOADS["pf66"]
+    g = _model(w)
+    say("pf66 mixed, 2 and 4 iterations")
+    e2, _, i2 = g.solve(32, 200, 384, 448, 1e-5, "mixed", max_iter=2, refine=False, check_every=1)
+    e4, _, i4 = g.solve(32, 200, 384, 448, 1e-5, "mixed", max_iter=4, refine=False, check_every=1)
+    say("pf66 lowest Ritz value after 2 / 4 iterations", e2[0], e4[0], "t", i2.t_total, i4.t_total)
+    assert not i4.converged and i4.iterations == 4
+    assert np.all(np.isfinite(e2[:64])) and np.all(np.isfinite(e4[:96]))
+    assert e4[0] <= e2[0] + 1e-5 * abs(e2[0])

@@ -1,6 +1,8 @@
 """Pins of the oracle's basis against numbers the paper prints (CPU only)."""
 import os
 
+import numpy as np
+
 import pytest
 
 from oracle.basis import ProductBasis, count_dim, count_sds, species_sectors
@@ -84,3 +86,14 @@ def test_tbme_counts_pn_formalism():
         t = random_tbme(orbits, 1)
         got = tuple(sum(1 for x in t if x[0] == ch) for ch in (0, 1, 2))
         assert got == want
+
+
+def test_combined_words_array_matches_list():
+    """The block-wise uint64 construction gives the same words, in the same order, as the plain one."""
+    from oracle.basis import ProductBasis
+    from workloads import PF_ORBITS, SD_ORBITS
+    for orbits, z, n, twoM, par in ((SD_ORBITS, 2, 2, 0, 0), (SD_ORBITS, 3, 2, 1, -1), (PF_ORBITS, 2, 3, 1, 0)):
+        b = ProductBasis(orbits, z, n, twoM, par)
+        arr = b.combined_words_array()
+        assert arr.dtype == np.uint64 and len(arr) == b.dim
+        assert [int(x) for x in arr] == b.combined_words()
