@@ -54,7 +54,7 @@ extern "C" {
 #define TRBL_E_TOO_MANY (-3)  /* more than 64 m-states per species */
 #define TRBL_E_NOMEM (-4)     /* host or device allocation failed */
 #define TRBL_E_DEVICE (-5)    /* HIP runtime error */
-#define TRBL_E_BREAKDOWN (-6) /* unrecoverable Lanczos breakdown */
+#define TRBL_E_BREAKDOWN (-6) /* unrecoverable breakdown: no direction left outside the basis */
 #define TRBL_E_STATE (-7)     /* call order (e.g. no Hamiltonian set) */
 
 typedef struct trbl_model trbl_model; /* opaque, library-owned */
@@ -126,7 +126,14 @@ int trbl_set_hamiltonian(trbl_model* m, const double* spe_p, const double* spe_n
 int trbl_apply(const trbl_model* m, int precision, int nb, const void* V, void* W, void* stream);
 
 /* Lowest n_eig eigenpairs by TRBL (Alg. 4, Sec. 3.4). evals: host n_eig doubles (ascending).
-   evecs: optional device [D][n_eig] FP64 Ritz vectors (orthonormal columns). info: optional. */
+   evecs: optional device [D][n_eig] FP64 Ritz vectors (orthonormal columns). info: optional.
+   The QR of each new block is Cholesky QR twice; a block that is numerically rank deficient
+   (start block with dependent columns, Krylov space exhausted) is factored column by column
+   and its deficient columns are replaced by random vectors orthogonal to the basis
+   (info->breakdowns counts them). Device memory: the basis [D][round4(l_m)] in FP64 (or FP32
+   with TRBL_MIXED), one FP64 [D][nb] block (plus an FP32 one in mixed mode), small tables.
+   Returns TRBL_NOT_CONVERGED after max_iter iterations with the current Ritz values (NaN
+   beyond the m available when fewer than n_eig exist yet). */
 int trbl_solve(const trbl_model* m, const trbl_opts* opts, double* evals, void* evecs, trbl_info* info);
 
 /* Gradient of sum_k w_k E_k (Hellmann-Feynman) with respect to every element of the last
