@@ -42,6 +42,9 @@ def parse():
     p.add_argument("--calib-copy", action="store_true",
                    help="with --hv-only: also run a plain 1 GiB device copy (counter calibration)")
     p.add_argument("--check-every", type=int, default=-1, help="convergence-test period; -1 = adaptive")
+    p.add_argument("--sweep", action="store_true",
+                   help="block-size sweep instead of the benchmark: H.V time and TRBL solve for the 32 lowest, "
+                        "nb = 1..32, l_s = 40, l_m = max(200, 40 + 10 nb)")
     return p.parse_args()
 
 
@@ -133,6 +136,27 @@ def cpu_baseline(w, iterations, seconds_target=12.0):
     }
 
 
+def sweep(model, w, torch, np):
+    """Trade-off of Sec. 4.2: block H.V time against nb (a line whose intercept is the fixed
+    generation cost) and iterations / time to the 32 lowest eigenpairs against nb."""
+    rows = []
+    for nb in (1, 2, 4, 8, 16, 32):
+        t_hv = hv_timing(model, nb, torch.float64, 10, torch)
+        lm = max(200, 40 + 10 * nb)  # room for ten blocks between restarts
+        ev, _, info = model.solve(nb, 32, 40, lm, 1e-8, "fp64", max_iter=20000, seed=1000, check_every=-1)
+        r = {"nb": nb, "l_m": lm, "hv_ms": t_hv * 1e3, "hv_ms_per_vector": t_hv * 1e3 / nb, "iterations": info.iterations,
+             "restarts": info.restarts, "converged": info.converged, "t_total_s": info.t_total, "t_hv_s": info.t_hv,
+             "t_orth_s": info.t_orth, "t_qr_s": info.t_qr, "t_eig_s": info.t_eig, "t_restart_s": info.t_restart,
+             "e0": float(ev[0]), "e31": float(ev[31])}
+        print("# " + json.dumps(r), file=sys.stderr, flush=True)
+        rows.append(r)
+    x = np.array([r["nb"] for r in rows], dtype=float)
+    y = np.array([r["hv_ms"] for r in rows])
+    slope, icpt = np.polyfit(x, y, 1)
+    print(json.dumps({"sweep": rows, "hv_fit_ms": {"intercept": icpt, "slope_per_vector": slope},
+                      "workload": w.name, "n_eig": 32, "l_s": 40, "l_m": "max(200, 40 + 10 nb)", "tol": 1e-8}))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -165,6 +189,10 @@ def main():
             torch.cuda.synchronize()
             dst.copy_(src)
             torch.cuda.synchronize()
+        return
+
+    if a.sweep:
+        sweep(model, w, torch, np)
         return
 
     def solve(prec):
