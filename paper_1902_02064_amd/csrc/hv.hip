@@ -116,6 +116,8 @@ static HVArgs<T> make_args(const Model& m, int nb, const void* V, int64_t ldv, v
   a.pj_start = d.pj_start.as<int>();
   a.pj_idx = d.pj_idx.as<int>();
   a.pj_meta = d.pj_meta.as<int>();
+  a.pg_start = d.pg_start.as<int>();
+  a.pg_desc = d.pg_desc.as<int>();
   a.nj_start = d.nj_start.as<int>();
   a.nj_pack = d.nj_pack.as<int2>();
   a.h_off = d.h_off.as<int>();

@@ -46,6 +46,8 @@ struct HVArgs {
   const int* pj_start;
   const int* pj_idx;
   const int* pj_meta;
+  const int* pg_start;  // per proton SD: first jump group
+  const int* pg_desc;   // jump groups, 4 ints each: class, first jump, end jump, source row
   const int* nj_start;  // class-major: [cls * (nn_total + 1) + g]
   const int2* nj_pack;  // (source local index, op << 1 | sign)
   const int* h_off;
@@ -184,26 +186,21 @@ __device__ __forceinline__ U ldu(const U* p, int64_t i) {
 
 // Proton jumps of one target SD are stored per class, sorted by source row; a group is a
 // run of jumps of one class with the same source row (several only for number operators).
+// The groups of every SD are listed on the host as (class, first jump, end jump, source row);
+// groups whose class has no source block in this product block are skipped.
 struct GroupIt {
-  int cls, jg, je, sb, p;
+  int g, cls, jg, je, sb, p;  // cls == ncl: no group left
 };
 
 template <class T>
-__device__ __forceinline__ GroupIt next_group(const HVArgs<T>& a, int b, int gp, int cls, int j) {
-  const int ncl = a.ncl;
-  while (cls < ncl) {
-    const int j1 = ldu(a.pj_start, gp * ncl + cls + 1);
-    const int sb = ldu(a.src_blk, b * ncl + cls);
-    if (sb >= 0 && j < j1) {
-      const int p = ldu(a.pj_idx, j);
-      int je = j + 1;
-      while (je < j1 && ldu(a.pj_idx, je) == p) je++;
-      return {cls, j, je, sb, p};
-    }
-    cls++;
-    if (cls < ncl) j = ldu(a.pj_start, gp * ncl + cls);
+__device__ __forceinline__ GroupIt group_at(const HVArgs<T>& a, int b, int g, int gend) {
+  for (; g < gend; g++) {
+    const int* d = a.pg_desc + 4 * (int64_t)g;
+    const int cls = ldu(d, 0);
+    const int sb = ldu(a.src_blk, b * a.ncl + cls);
+    if (sb >= 0) return {g, cls, ldu(d, 1), ldu(d, 2), sb, ldu(d, 3)};
   }
-  return {ncl, 0, 0, -1, 0};
+  return {gend, a.ncl, 0, 0, -1, 0};
 }
 
 constexpr int MAXE = 8;           // neutron jumps per (target, class) kept in registers
@@ -256,7 +253,8 @@ __global__ __launch_bounds__(NTB) void hv_rows_kernel(HVArgs<T> a) {
     else stage_sync<T, C>(dst, src, a.ldv, rows, cvalid);
   };
 
-  GroupIt it = next_group(a, b, gp, 0, ldu(a.pj_start, gp * ncl));
+  const int gend = ldu(a.pg_start, gp + 1);
+  GroupIt it = group_at(a, b, ldu(a.pg_start, gp), gend);
   stage_row(B0, off + (int64_t)pl * dn, dn);
   if (it.cls < ncl) stage_row(B1, a.blk_off[it.sb] + (int64_t)it.p * a.blk_dn[it.sb], a.blk_dn[it.sb]);
   __builtin_amdgcn_s_waitcnt(0);
@@ -315,7 +313,7 @@ __global__ __launch_bounds__(NTB) void hv_rows_kernel(HVArgs<T> a) {
       __builtin_amdgcn_s_waitcnt(0);  // entries in registers before any DMA is in flight
       __syncthreads();
     }
-    const GroupIt nx = next_group(a, b, gp, it.cls, it.je);
+    const GroupIt nx = group_at(a, b, it.g + 1, gend);
     if (nx.cls < ncl)
       stage_row(wr, ldu(a.blk_off, nx.sb) + (int64_t)nx.p * ldu(a.blk_dn, nx.sb), ldu(a.blk_dn, nx.sb));
     // hr points into LDS or into global memory: two copies of the loop keep every load

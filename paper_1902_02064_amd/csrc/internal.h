@@ -103,6 +103,7 @@ struct DeviceTables {
   DevBuf psec_tm, psec_par, nsec_tm, nsec_par;
   // jumps
   DevBuf pj_start, pj_idx, pj_meta, nj_start, nj_idx, nj_meta, pj_pack, nj_pack;  // nj_* class-major
+  DevBuf pg_start, pg_desc;  // per proton SD: jump groups (class, first, end, source row) as int4
   DevBuf h_off, h_ncol, h64, h32;
   DevBuf pp_ptr, pp_col, pp_v64, pp_v32, nn_ptr, nn_col, nn_v64, nn_v32;
   DevBuf pe_off, pe_w, pe_col, pe_v64, pe_v32, ne_off, ne_w, ne_col, ne_v64, ne_v32;  // sliced ELL

@@ -575,6 +575,24 @@ void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const
       pack[2 * q + 1] = jmeta[q];
     }
     (s == 0 ? m.dt.pj_start : m.dt.nj_start).upload(start);
+    if (s == 0) {
+      // proton jump groups of every SD: runs of jumps of one class with one source row,
+      // class by class, as (class, first jump, end jump, source row)
+      std::vector<int> gstart(nsd + 1, 0), gdesc;
+      for (int64_t g = 0; g < nsd; g++) {
+        gstart[g] = (int)(gdesc.size() / 4);
+        for (int c = 0; c < ncl; c++)
+          for (int j = start[g * ncl + c]; j < start[g * ncl + c + 1];) {
+            int je = j + 1;
+            while (je < start[g * ncl + c + 1] && jidx[je] == jidx[j]) je++;
+            gdesc.insert(gdesc.end(), {c, j, je, jidx[j]});
+            j = je;
+          }
+      }
+      gstart[nsd] = (int)(gdesc.size() / 4);
+      m.dt.pg_start.upload(gstart);
+      m.dt.pg_desc.upload(gdesc);
+    }
     (s == 0 ? m.dt.pj_idx : m.dt.nj_idx).upload(jidx);
     (s == 0 ? m.dt.pj_meta : m.dt.nj_meta).upload(jmeta);
     (s == 0 ? m.dt.pj_pack : m.dt.nj_pack).upload(pack);
