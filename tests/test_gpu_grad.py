@@ -155,3 +155,33 @@ def test_autograd_function(sd22, keep):
     assert np.abs(v.grad.numpy() - ov).max() <= 1e-8 * np.abs(ov).max()
     assert np.abs(sp.grad.numpy() - os_[:3]).max() <= 1e-8 * np.abs(os_).max()
     assert np.abs(sn.grad.numpy() - os_[3:]).max() <= 1e-8 * np.abs(os_).max()
+
+
+def test_grad_sd66_finite_differences():
+    """Gradient workload (sd 6+6, D = 93,710, 20 lowest, nb = 8): central differences with h = 1e-5
+    of sum_k w_k E_k from FP64 solves at rho <= 1e-10 |H|, for elements of all three channels."""
+    w = WORKLOADS["sd66"]
+    tb = w.tbme()
+    g, _ = pair(w.orbits, w.n_prot, w.n_neut, w.twoM, tb, w.spe, w.spe, oracle=False)
+    wt = grad_weights(w.n_eig, w.extra["grad_weight_seed"])
+    ev, X, info = g.solve(w.nb, w.n_eig, w.l_s, w.l_m, w.tol, "fp64", vectors=True)
+    assert info.converged
+    gv, gs = g.tbme_grad(wt, evecs=X)
+    h = w.extra["fd_step"]
+
+    def f(tbl):
+        g.set_hamiltonian(w.spe, w.spe, tbl)
+        e, _, inf = g.solve(w.nb, w.n_eig, w.l_s, w.l_m, w.tol, "fp64")
+        assert inf.converged
+        return wt @ e
+
+    chans = [next(i for i, t in enumerate(tb) if t[0] == c) for c in (0, 1, 2)]
+    picks = chans + [57, 120, len(tb) - 1]
+    for t in picks:
+        up, dn = list(tb), list(tb)
+        up[t] = tb[t][:6] + (tb[t][6] + h,)
+        dn[t] = tb[t][:6] + (tb[t][6] - h,)
+        fd = (f(up) - f(dn)) / (2 * h)
+        say("sd66 element", t, tb[t][:6], "fd", fd, "grad", gv[t])
+        assert abs(fd - gv[t]) <= 1e-5 * max(abs(gv[t]), 1e-3 * np.abs(gv).max())
+    g.set_hamiltonian(w.spe, w.spe, tb)
