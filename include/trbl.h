@@ -60,6 +60,7 @@ extern "C" {
 typedef struct trbl_model trbl_model; /* opaque, library-owned */
 
 typedef enum { TRBL_FP64 = 0, TRBL_MIXED = 1 } trbl_precision;
+typedef enum { TRBL_CONV_RESIDUAL = 0, TRBL_CONV_RITZ_CHANGE = 1 } trbl_criterion;
 
 typedef struct {
   int n, l, twoj; /* radial number, orbital l, 2j */
@@ -88,6 +89,9 @@ typedef struct {
                       restart); 0 or 1 = every iteration, as in Alg. 4; negative = adaptive:
                       the next test is scheduled from the observed decay of the largest
                       residual (every restart still tests) */
+  int criterion;   /* TRBL_CONV_RESIDUAL (0): rho_i <= tol * max|theta|;
+                      TRBL_CONV_RITZ_CHANGE (1): the paper's test of Sec. 4.1, the n_eig lowest Ritz
+                      values move by at most tol (absolute) between two consecutive tests */
 } trbl_opts;
 
 typedef struct {

@@ -40,7 +40,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("nb", ctypes.c_int), ("n_eig", ctypes.c_int), ("l_s", ctypes.c_int), ("l_m", ctypes.c_int),
                 ("max_iter", ctypes.c_int), ("tol", ctypes.c_double), ("precision", ctypes.c_int),
                 ("refine", ctypes.c_int), ("seed", ctypes.c_uint64), ("v0", ctypes.c_void_p),
-                ("stream", ctypes.c_void_p), ("check_every", ctypes.c_int)]
+                ("stream", ctypes.c_void_p), ("check_every", ctypes.c_int), ("criterion", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -205,7 +205,8 @@ class Model:
         return W
 
     # -- eigensolver
-    def _opts(self, nb, n_eig, l_s, l_m, tol, precision, max_iter, seed, v0, refine, check_every=1):
+    def _opts(self, nb, n_eig, l_s, l_m, tol, precision, max_iter, seed, v0, refine, check_every=1,
+              criterion="residual"):
         o = Opts()
         o.nb, o.n_eig, o.l_s, o.l_m, o.max_iter = nb, n_eig, l_s, l_m, max_iter
         o.tol = tol
@@ -215,13 +216,14 @@ class Model:
         o.v0 = None if v0 is None else v0.data_ptr()
         o.stream = _stream().value
         o.check_every = check_every
+        o.criterion = {"residual": 0, "ritz_change": 1}[criterion]
         return o
 
     def solve(self, nb, n_eig, l_s, l_m, tol, precision="fp64", max_iter=5000, seed=1000, v0=None,
-              refine=True, vectors=False, check_every=1):
+              refine=True, vectors=False, check_every=1, criterion="residual"):
         """Lowest eigenpairs by TRBL (Alg. 4). Returns (evals, evecs or None, SolveInfo)."""
         import torch
-        o = self._opts(nb, n_eig, l_s, l_m, tol, precision, max_iter, seed, v0, refine, check_every)
+        o = self._opts(nb, n_eig, l_s, l_m, tol, precision, max_iter, seed, v0, refine, check_every, criterion)
         ev = (ctypes.c_double * n_eig)()
         res = (ctypes.c_double * n_eig)()
         info = Info()

@@ -56,6 +56,8 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
   TRBL_REQUIRE(ls + 2 * nb <= lm && (int64_t)lm <= D, TRBL_E_INVALID, "need l_s + 2 nb <= l_m <= D");
   TRBL_REQUIRE(lm <= 768, TRBL_E_INVALID, "l_m above 768 is not supported");
   TRBL_REQUIRE(o.tol > 0.0 && o.max_iter >= 1, TRBL_E_INVALID, "bad tol or max_iter");
+  TRBL_REQUIRE(o.criterion == TRBL_CONV_RESIDUAL || o.criterion == TRBL_CONV_RITZ_CHANGE, TRBL_E_INVALID,
+               "unknown convergence criterion");
   hipStream_t st = (hipStream_t)o.stream;
   // an FP32 residual cannot fall far below the FP32 rounding of H.V: floor the tolerance
   const double tol = mixed ? std::max(o.tol, 1e-5) : o.tol;
@@ -190,6 +192,7 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
   bool converged = false, last_orth = false;
   int next_check = 1, it_prev = 0;  // adaptive convergence-test schedule (check_every < 0)
   double r_prev = -1.0;
+  std::vector<double> th_prev;  // Ritz values at the previous test (Ritz-change criterion)
   int nchk = 0;
   for (it = 1; it <= o.max_iter; it++) {
     k++;
@@ -267,8 +270,18 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
     hnorm = std::max(hnorm, std::max(std::fabs(th[0]), std::fabs(tmax)));
     bool ok = nchk == neig;
     int nconv_it = 0;
-    for (int i = 0; i < nchk; i++) nconv_it += rh[i] <= tol * hnorm;
-    for (int i = 0; ok && i < nchk; i++) ok = rh[i] <= tol * hnorm;
+    if (o.criterion == TRBL_CONV_RITZ_CHANGE) {
+      // Sec. 4.1: the wanted Ritz values stop moving (absolute change <= tol between tests)
+      for (int i = 0; i < nchk; i++) {
+        const bool still = (int)th_prev.size() == nchk && std::fabs(th[i] - th_prev[i]) <= o.tol;
+        nconv_it += still;
+        ok = ok && still;
+      }
+      th_prev.assign(th.begin(), th.begin() + nchk);
+    } else {
+      for (int i = 0; i < nchk; i++) nconv_it += rh[i] <= tol * hnorm;
+      for (int i = 0; ok && i < nchk; i++) ok = rh[i] <= tol * hnorm;
+    }
     if (verbose) {
       double rmax = 0.0;
       for (int i = 0; i < nchk; i++) rmax = std::max(rmax, rh[i]);

@@ -118,3 +118,19 @@ def test_check_schedules_agree(sd22, every):
     ev, _, info = g.solve(w.nb, w.n_eig, w.l_s, w.l_m, w.tol, "fp64", check_every=every)
     assert info.converged
     assert np.abs(ev - e[:w.n_eig]).max() <= 1e-8 * np.abs(e[:w.n_eig]).max()
+
+
+def test_ritz_change_criterion(sd22):
+    """The paper's stopping rule (Sec. 4.1): Ritz values change by < 1e-6 between consecutive
+    iterations. It stops earlier than the residual test at 1e-8 and is looser: the Ritz values
+    are upper bounds and lie within the residual bound of the exact eigenvalues."""
+    w, g, o, H, e = sd22
+    ev, X, info = g.solve(w.nb, w.n_eig, w.l_s, w.l_m, 1e-6, "fp64", vectors=True, check_every=1,
+                          criterion="ritz_change")
+    evr, _, infor = g.solve(w.nb, w.n_eig, w.l_s, w.l_m, w.tol, "fp64", check_every=1)
+    say("ritz-change iterations", info.iterations, "residual-test iterations", infor.iterations)
+    assert info.converged and info.iterations <= infor.iterations
+    assert np.all(ev >= e[:w.n_eig] - 1e-10)
+    Xh = X.cpu().numpy()
+    res = np.linalg.norm(H @ Xh - Xh * ev, axis=0)
+    assert np.all(np.abs(ev - e[:w.n_eig]) <= res + 1e-10)
