@@ -147,6 +147,13 @@ int trbl_solve(const trbl_model* m, const trbl_opts* opts, double* evals, void* 
 int trbl_tbme_grad(const trbl_model* m, const trbl_opts* opts, int n_eig, const double* w,
                    const void* evecs, double* grad_v, double* grad_spe);
 
+/* Expectation values <x_c| H |x_c> of the model's Hamiltonian for the n columns of X (device
+   [D][n] FP64, the model's basis order), into out (host, n doubles): block H.V (App. B) and
+   column products on the device. With H = J^2 written as an interaction (one-body part j(j+1)
+   in the single-particle energies, two-body part J(J+1) - ja(ja+1) - jb(jb+1) on diagonal pair
+   elements) this gives <J^2> of Ritz vectors. Allocates one [D][min(n,64)] FP64 block. */
+int trbl_expect(const trbl_model* m, int n, const void* X, double* out, void* stream);
+
 /* Message of the last failing call on this thread. */
 const char* trbl_last_error(void);
 

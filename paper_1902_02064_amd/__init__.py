@@ -77,6 +77,7 @@ def load():
         "trbl_apply": ([P, I, I, P, P, P], I),
         "trbl_solve": ([P, ctypes.POINTER(Opts), P, P, ctypes.POINTER(Info)], I),
         "trbl_tbme_grad": ([P, ctypes.POINTER(Opts), I, P, P, P, P], I),
+        "trbl_expect": ([P, I, P, P, P], I),
         "trbl_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -203,6 +204,15 @@ class Model:
         assert W.shape == V.shape and W.dtype == V.dtype and W.is_contiguous()
         _check(load().trbl_apply(self._h, prec, V.shape[1], _ptr(V), _ptr(W), _stream()))
         return W
+
+    def expect(self, X):
+        """<x_c|H|x_c> for the columns of X (device [D][n] float64), computed on the device."""
+        import torch
+        assert X.is_cuda and X.dtype == torch.float64 and X.dim() == 2 and X.shape[0] == self.dim
+        X = X.contiguous()
+        out = np.zeros(X.shape[1])
+        _check(load().trbl_expect(self._h, X.shape[1], _ptr(X), out.ctypes.data_as(ctypes.c_void_p), _stream()))
+        return out
 
     # -- eigensolver
     def _opts(self, nb, n_eig, l_s, l_m, tol, precision, max_iter, seed, v0, refine, check_every=1,

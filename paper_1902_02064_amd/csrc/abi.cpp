@@ -2,7 +2,7 @@
 // capture, and dispatch to the host set-up, the H.V kernels and the solver.
 #include <cstring>
 
-#include "internal.h"
+#include "dense.h"
 
 namespace trbl {
 static thread_local std::string g_last_error;
@@ -132,6 +132,30 @@ int trbl_apply(const trbl_model* h, int precision, int nb, const void* V, void* 
     TRBL_REQUIRE(h != nullptr, TRBL_E_INVALID, "NULL model");
     TRBL_REQUIRE(precision == TRBL_FP64 || precision == TRBL_MIXED, TRBL_E_INVALID, "bad precision");
     trbl::launch_apply(h->m, precision, nb, V, nb, W, nb, (hipStream_t)stream);
+    return TRBL_OK;
+  });
+}
+
+int trbl_expect(const trbl_model* h, int n, const void* X, double* out, void* stream) {
+  return guarded([&] {
+    TRBL_REQUIRE(h && X && out && n >= 1, TRBL_E_INVALID, "bad argument");
+    const trbl::Model& m = h->m;
+    hipStream_t s = (hipStream_t)stream;
+    const int cw = 64;
+    trbl::DevBuf Wb, Cb;
+    Wb.alloc((size_t)m.dim * std::min(n, cw) * sizeof(double));
+    Cb.alloc((size_t)cw * cw * sizeof(double));
+    trbl::Scratch sc;
+    std::vector<double> ch((size_t)cw * cw);
+    const double* Xd = static_cast<const double*>(X);
+    for (int c0 = 0; c0 < n; c0 += cw) {
+      const int w = std::min(cw, n - c0);
+      trbl::launch_apply(m, TRBL_FP64, w, Xd + c0, n, Wb.p, w, s);
+      trbl::tn<double, double>(Xd + c0, n, w, Wb.as<double>(), w, w, m.dim, Cb.as<double>(), sc, s);
+      TRBL_HIP(hipMemcpyAsync(ch.data(), Cb.p, (size_t)w * w * sizeof(double), hipMemcpyDeviceToHost, s));
+      TRBL_HIP(hipStreamSynchronize(s));
+      for (int j = 0; j < w; j++) out[c0 + j] = ch[(size_t)j * w + j];
+    }
     return TRBL_OK;
   });
 }

@@ -89,3 +89,18 @@ def test_pf66_mixed_iterations_fit_and_descend():
     assert not i4.converged and i4.iterations == 4
     assert np.all(np.isfinite(e2[:64])) and np.all(np.isfinite(e4[:96]))
     assert e4[0] <= e2[0] + 1e-5 * abs(e2[0])
+
+
+def test_pf44_ritz_vectors_have_integer_j():
+    """pf44 at full size: <J^2> of the 100 Ritz vectors is J(J+1) with integer J."""
+    from workloads import jsquared_spe, jsquared_tbme
+    w = WORKLOADS["pf44"]
+    g = _model(w)
+    ev, X, info = g.solve(w.nb, w.n_eig, w.l_s, w.l_m, w.tol, "fp64", vectors=True, check_every=-1)
+    assert info.converged
+    gj, _ = pair(w.orbits, w.n_prot, w.n_neut, w.twoM, jsquared_tbme(w.orbits), jsquared_spe(w.orbits),
+                 jsquared_spe(w.orbits), oracle=False)
+    j2 = gj.expect(X)
+    J = (-1 + np.sqrt(1 + 4 * j2)) / 2
+    say("pf44 J values", np.round(J, 4)[:20], "max dev", np.abs(J - np.round(J)).max())
+    assert np.abs(J - np.round(J)).max() <= 1e-4

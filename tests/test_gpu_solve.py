@@ -134,3 +134,22 @@ def test_ritz_change_criterion(sd22):
     Xh = X.cpu().numpy()
     res = np.linalg.norm(H @ Xh - Xh * ev, axis=0)
     assert np.all(np.abs(ev - e[:w.n_eig]) <= res + 1e-10)
+
+
+def _jsq_model(orbits, z, n, twoM):
+    from workloads import jsquared_spe, jsquared_tbme
+    g, _ = pair(orbits, z, n, twoM, jsquared_tbme(orbits), jsquared_spe(orbits), jsquared_spe(orbits),
+                oracle=False)
+    return g
+
+
+def test_ritz_vectors_carry_good_angular_momentum(sd22):
+    """Rotational invariance: every Ritz vector of a random J-coupled interaction is an eigenvector
+    of J^2, <J^2> = J(J+1) with integer J (a wrong sign, phase or Clebsch-Gordan coefficient in
+    the device H.V breaks this)."""
+    w, g, o, H, e = sd22
+    ev, X, info = g.solve(w.nb, w.n_eig, w.l_s, w.l_m, 1e-10, "fp64", vectors=True)
+    j2 = _jsq_model(w.orbits, w.n_prot, w.n_neut, w.twoM).expect(X)
+    J = (-1 + np.sqrt(1 + 4 * j2)) / 2
+    say("sd22 <J^2>", np.round(j2, 6))
+    assert np.abs(J - np.round(J)).max() <= 1e-6
