@@ -25,6 +25,24 @@ __device__ __forceinline__ double ld(const T* p) {
   return (double)(*p);
 }
 
+// four consecutive values of a row in their own type; masked beyond `valid`
+template <class T>
+__device__ __forceinline__ void ld4raw(const T* p, int valid, T out[4]) {
+  if (valid >= 4) {
+    if constexpr (sizeof(T) == 8) {
+      const double2* q = reinterpret_cast<const double2*>(p);
+      double2 x = q[0], y = q[1];
+      out[0] = x.x; out[1] = x.y; out[2] = y.x; out[3] = y.y;
+    } else {
+      float4 x = *reinterpret_cast<const float4*>(p);
+      out[0] = x.x; out[1] = x.y; out[2] = x.z; out[3] = x.w;
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < 4; t++) out[t] = (t < valid) ? p[t] : T(0);
+  }
+}
+
 // four consecutive values of a row, widened; masked beyond `valid`
 template <class T>
 __device__ __forceinline__ void ld4(const T* p, int valid, double out[4]) {
@@ -292,6 +310,120 @@ __global__ __launch_bounds__(WAVES * 64) void update_kernel(const TA* __restrict
       out[e] = s;
     }
   }
+}
+
+// ------------------------------------------------------------------ first CGS pass, fused
+// Bout = Bin - A C together with part[g] = A^T Bout over the workgroup's rows, reading A once
+// (nb <= 16, m <= 512). A tile of 16 rows is split by columns over 16 waves (at most 2 chunks
+// of 16 columns each); each wave keeps its slice of C in registers, sums its share of A C into
+// LDS, and parks its slice of the tile in LDS (rows padded by 4 values against bank conflicts)
+// to read it back transposed for the projection, 2 consecutive columns per lane. The loads of
+// A and Bin run PFD tiles ahead of the arithmetic, in PFD register buffers. Only the
+// cross-wave sum needs the workgroup barriers.
+template <class TA, class TI, int PFD>
+__global__ __launch_bounds__(1024) void cgs_fused_kernel(const TA* __restrict__ A, int64_t lda, int m,
+                                                         const double* __restrict__ C, const TI* Bin, int64_t ldi,
+                                                         double* Bout, int64_t ldo, int nb, int64_t D,
+                                                         double* __restrict__ part) {
+  constexpr int WAVES = 16, KC = 2;
+  extern __shared__ double lds[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int mt = (m + 15) >> 4;
+  const int mp = mt * 16, asp = mp + 4;
+  const int cpw = (mt + WAVES - 1) / WAVES;  // 16-column chunks per wave, <= KC
+  const int kw0 = min(mp, wave * cpw * 16), kw1 = min(mp, kw0 + cpw * 16);
+  const int nch = (kw1 - kw0) >> 4;
+  const int erow = threadIdx.x >> 4, ec = threadIdx.x & 15;  // threads < 256: one element of the tile
+  double* As = lds;                    // 16 x asp: the tile of A
+  double* red = As + 16 * asp;         // WAVES x 16 x 16: partial products of the waves
+  double* Wt = red + WAVES * 16 * 16;  // 16 x 16: the updated rows
+  double cr[KC][4];
+#pragma unroll
+  for (int j = 0; j < KC; j++)
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      const int k = kw0 + 16 * j + 4 * lk + t;
+      cr[j][t] = (j < nch && k < m && li < nb) ? C[k * nb + li] : 0.0;
+    }
+  d4 pacc[2] = {d4{0, 0, 0, 0}, d4{0, 0, 0, 0}};
+  const int64_t ntiles = (D + 15) / 16;
+  auto load = [&](int64_t tile, TA (&a)[KC][4], TI& bn) {
+    if (tile >= ntiles) return;
+    const int64_t ra = tile * 16 + li;
+#pragma unroll
+    for (int j = 0; j < KC; j++) {
+      const int kk = kw0 + 16 * j + 4 * lk;
+      if (j < nch && ra < D && kk < m) ld4raw(A + ra * lda + kk, m - kk, a[j]);
+      else a[j][0] = a[j][1] = a[j][2] = a[j][3] = TA(0);
+    }
+    const int64_t r = tile * 16 + erow;
+    bn = (threadIdx.x < 256 && r < D && ec < nb) ? Bin[r * ldi + ec] : TI(0);
+  };
+  // one tile from its buffer; the buffer is then refilled PFD tiles ahead
+  auto body = [&](int64_t tile, TA (&a)[KC][4], TI& bn) {
+    d4 acc = d4{0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < KC; j++) {
+      if (j >= nch) continue;
+      const int kk = kw0 + 16 * j + 4 * lk;
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        const double x = (double)a[j][t];
+        As[li * asp + kk + t] = x;
+        acc = mfma(x, cr[j][t], acc);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; v++) red[(wave * 16 + lk + 4 * v) * 16 + li] = acc[v];
+    const double bcur = (double)bn;
+    load(tile + (int64_t)PFD * gridDim.x, a, bn);
+    __syncthreads();
+    if (threadIdx.x < 256) {
+      const int64_t r = tile * 16 + erow;
+      double sum = 0.0;
+#pragma unroll
+      for (int w = 0; w < WAVES; w++) sum += red[(w * 16 + erow) * 16 + ec];
+      double val = 0.0;
+      if (r < D && ec < nb) {
+        val = bcur - sum;
+        Bout[r * ldo + ec] = val;
+      }
+      Wt[threadIdx.x] = val;
+    }
+    __syncthreads();
+    // Wt and red are rewritten only after the next tile's first barrier, which every wave reaches
+    // after this projection; each wave reads back only the slice of As it wrote itself.
+    if (nch > 0) {
+      const int c0 = kw0 + 2 * li;
+#pragma unroll
+      for (int sq = 0; sq < 4; sq++) {
+        const int row = 4 * sq + lk;
+        double a2[2];
+#pragma unroll
+        for (int t = 0; t < 2; t++) a2[t] = c0 < kw1 ? As[row * asp + c0 + t] : 0.0;
+        const double bop = Wt[row * 16 + li];
+#pragma unroll
+        for (int t = 0; t < 2; t++) pacc[t] = mfma(a2[t], bop, pacc[t]);
+      }
+    }
+  };
+  TA a0[KC][4], a1[KC][4];
+  TI b0 = TI(0), b1 = TI(0);
+  load(blockIdx.x, a0, b0);
+  if (PFD == 2) load(blockIdx.x + gridDim.x, a1, b1);
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += (int64_t)PFD * gridDim.x) {
+    body(tile, a0, b0);
+    if (PFD == 2 && tile + gridDim.x < ntiles) body(tile + gridDim.x, a1, b1);
+  }
+  double* out = part + (int64_t)blockIdx.x * m * nb;
+#pragma unroll
+  for (int t = 0; t < 2; t++)
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+      const int col = kw0 + 2 * (lk + 4 * v) + t;
+      if (col < m && col < kw1 && li < nb) out[(int64_t)col * nb + li] = pacc[t][v];
+    }
 }
 
 // ------------------------------------------------------------------ Bout = Bin R  (R: nb x nb), optional Gram partial
@@ -602,6 +734,22 @@ void update(const TA* A, int64_t lda, int m, const double* C, const TI* Bin, int
             int nb, int64_t D, int mode, double* Pout, Scratch& s, hipStream_t st) {
   TRBL_REQUIRE(m >= 1 && m <= 768 && nb >= 1 && nb <= 64, TRBL_E_INVALID, "projection shape out of range");
   const int mt = (m + 15) / 16, ct = (nb + 15) / 16, npan = (m + 63) / 64;
+  if (mode == 1 && mt <= 32 && ct == 1 && Bin) {  // one pass over A for the update and the projection
+    const size_t shmf = (size_t)(16 * (mt * 16 + 4) + 16 * 16 * 16 + 16 * 16) * sizeof(double);
+    const int G = grid_for(D, 16, 256);  // one resident workgroup of 16 waves per CU
+    double* part = s.partials((size_t)G * m * nb);
+    constexpr int PFD = sizeof(TA) == 4 ? 2 : 1;  // FP32 panels: half the bytes per tile, twice the tiles in flight
+    hipLaunchKernelGGL((cgs_fused_kernel<TA, TI, PFD>), dim3(G), dim3(1024), shmf, st, A, lda, m, C, Bin, ldi, Bout,
+                       ldo, nb, D, part);
+    const int64_t plen = (int64_t)m * nb;
+    if (Pout)
+      hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((plen + 15) / 16)), dim3(256), 0, st, part, G, plen,
+                         Pout);
+    s.last_G = G;
+    s.last_part = part;
+    TRBL_HIP(hipGetLastError());
+    return;
+  }
   auto shm_for = [&](int waves) {
     size_t b = (size_t)(mt * 16 * ct * 16 + waves * 16 * ct * 16) * sizeof(double);
     return std::max(b, (size_t)ct * 16 * ct * 16 * sizeof(double));
