@@ -1,12 +1,15 @@
 // Symmetric eigensolver for the small projected matrix T of TRBL (Alg. 4:
-// "diagonalise T^(k)"; restart equations of Sec. 3.4), FP64, one workgroup.
+// "diagonalise T^(k)"; restart equations of Sec. 3.4), FP64, in five launches:
 //
-//   1. Householder reduction to tridiagonal form (A = Q Tri Q^T), reflectors kept;
-//   2. eigenvalues by Sturm-sequence bisection (one thread per wanted index);
+//   1. Householder reduction to tridiagonal form (A = Q Tri Q^T), reflectors kept
+//      (one workgroup: every step depends on the previous one);
+//   2. eigenvalues by Sturm-sequence multisection, a group of threads per wanted index,
+//      spread over workgroups;
 //   3. eigenvectors of Tri by inverse iteration with a pivoted LU of (Tri - lambda I),
-//      one thread per vector, then Cholesky QR (twice) of the vector block so that
-//      vectors of close eigenvalues are orthonormal;
-//   4. back-transformation U = Q Z.
+//      one thread per vector with its LU in LDS, spread over workgroups;
+//   4. Cholesky QR (twice) of the vector block so that vectors of close eigenvalues are
+//      orthonormal (one workgroup, skipped when they already are);
+//   5. back-transformation U = Q Z, one workgroup per block of 16 columns.
 // Textbook methods (Householder; Sturm-sequence bisection; inverse iteration),
 // written for this library.
 #include <cfloat>
@@ -59,18 +62,15 @@ __device__ static int sturm(const double* d, const double* e2, int n, double x, 
 
 constexpr int EIG_BIG = 20 * EIG_NMAX;  // shared work area (doubles)
 
-__global__ __launch_bounds__(EIG_THREADS) void symeig_kernel(const double* __restrict__ T, int ldt, int n, int nvec,
-                                                             int orth, double* __restrict__ theta,
-                                                             double* __restrict__ U, int ldu, double* __restrict__ A,
-                                                             double* __restrict__ Z, double* __restrict__ LU) {
-  // work area: panel vectors of the blocked reduction, then row chunks of Z (Cholesky QR),
-  // then a column block of Z plus staged reflectors (back-transformation)
-  __shared__ double big[EIG_BIG];
+// tridiagonal (d, e, e2) and the bisection interval: de[0..n) = d, de[n..2n) = e,
+// de[2n..3n) = e^2, de[3n..3n+4) = (lower bound, upper bound, norm bound, pivmin)
+__global__ __launch_bounds__(EIG_THREADS) void tridiag_kernel(const double* __restrict__ T, int ldt, int n,
+                                                              double* __restrict__ A, double* __restrict__ de) {
+  __shared__ double big[2 * PNB * EIG_NMAX];
   double(*Vp)[EIG_NMAX] = reinterpret_cast<double(*)[EIG_NMAX]>(big);
   double(*Wp)[EIG_NMAX] = reinterpret_cast<double(*)[EIG_NMAX]>(big + PNB * EIG_NMAX);
-  __shared__ double d[EIG_NMAX], e[EIG_NMAX], e2[EIG_NMAX], vv[EIG_NMAX], pw[EIG_NMAX], lam[EIG_NMAX];
-  __shared__ double part[EIG_THREADS], sx[EIG_THREADS];
-  __shared__ int scnt[EIG_THREADS];
+  __shared__ double d[EIG_NMAX], e[EIG_NMAX], e2[EIG_NMAX], vv[EIG_NMAX], pw[EIG_NMAX];
+  __shared__ double part[EIG_THREADS];
   __shared__ double red[32], wlo[16], whi[16], wnm[16], xw[PNB], yv[PNB];
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6, nwave = nthr >> 6;
@@ -218,14 +218,40 @@ __global__ __launch_bounds__(EIG_THREADS) void symeig_kernel(const double* __res
   const double pivmin = DBL_MIN * fmax(1.0, tnorm * tnorm);
   glo -= 2.0 * DBL_EPSILON * tnorm * n + pivmin;
   ghi += 2.0 * DBL_EPSILON * tnorm * n + pivmin;
+  for (int i = tid; i < n; i += nthr) {
+    de[i] = d[i];
+    de[n + i] = e[i];
+    de[2 * n + i] = e2[i];
+  }
+  if (tid == 0) {
+    de[3 * n] = glo;
+    de[3 * n + 1] = ghi;
+    de[3 * n + 2] = tnorm;
+    de[3 * n + 3] = pivmin;
+  }
+}
 
-  // ---- 2. eigenvalues by multisection: a group of tpe threads refines one eigenvalue (the
-  // nvec lowest and the largest); each round its threads take Sturm counts at tpe interior
-  // points of the group's interval, which shrinks by a factor tpe + 1.
+// eigenvalues by multisection: a group of BIS_TPE threads refines one eigenvalue (the nvec
+// lowest and the largest); each round its threads take Sturm counts at BIS_TPE interior points
+// of the group's interval, which shrinks by a factor BIS_TPE + 1. Launch: 256 threads per
+// workgroup, ceil((nvec + 1) * BIS_TPE / 256) workgroups.
+constexpr int BIS_TPE = 32;
+__global__ __launch_bounds__(256) void bisect_kernel(const double* __restrict__ de, int n, int nvec,
+                                                     double* __restrict__ theta) {
+  __shared__ double d[EIG_NMAX], e2[EIG_NMAX];
+  __shared__ double sx[256];
+  __shared__ int scnt[256];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  for (int i = tid; i < n; i += nthr) {
+    d[i] = de[i];
+    e2[i] = de[2 * n + i];
+  }
+  double glo = de[3 * n], ghi = de[3 * n + 1];
+  const double pivmin = de[3 * n + 3];
+  __syncthreads();
   {
-    const int nwant = nvec < n ? nvec + 1 : nvec;
-    const int tpe = max(1, min(32, nthr / nwant));
-    const int q = tid / tpe, sub = tid - (tid / tpe) * tpe;
+    const int tpe = BIS_TPE;
+    const int q = blockIdx.x * (nthr / tpe) + tid / tpe, sub = tid % tpe;
     const int want = q < nvec ? q : ((q == nvec && nvec < n) ? n - 1 : -1);
     double lo = glo, hi = ghi;
     const int rounds = (int)ceil(64.0 / log2((double)tpe + 1.0)) + 1;
@@ -244,8 +270,8 @@ __global__ __launch_bounds__(EIG_THREADS) void symeig_kernel(const double* __res
       if (live) {
         double nlo = lo, nhi = hi;
         for (int t = 0; t < tpe; t++) {
-          const double xt = sx[q * tpe + t];
-          if (scnt[q * tpe + t] > want) nhi = fmin(nhi, xt);
+          const double xt = sx[(tid / tpe) * tpe + t];
+          if (scnt[(tid / tpe) * tpe + t] > want) nhi = fmin(nhi, xt);
           else nlo = fmax(nlo, xt);
         }
         lo = nlo;
@@ -253,26 +279,39 @@ __global__ __launch_bounds__(EIG_THREADS) void symeig_kernel(const double* __res
       }
       __syncthreads();
     }
-    if (want >= 0 && sub == 0) {
-      const double l = 0.5 * (lo + hi);
-      lam[want] = l;
-      theta[want] = l;
-    }
+    if (want >= 0 && sub == 0) theta[want] = 0.5 * (lo + hi);
   }
-  __syncthreads();
+}
 
-  // ---- 3. inverse iteration, one thread per wanted vector. The pivoted LU of (Tri - lambda I)
-  // is computed with the running pivot row kept in registers and written out once; the
-  // solves stream through it. Vectors are orthonormalised afterwards (Cholesky QR).
-  // LU layout: array q, entry i of vector j at LU[(q * n + i) * nvec + j] (coalesced over j).
-  for (int j = tid; j < nvec; j += nthr) {
-    double* dl = LU + (0 * (int64_t)n) * nvec + j;
-    double* dd = LU + (1 * (int64_t)n) * nvec + j;
-    double* du = LU + (2 * (int64_t)n) * nvec + j;
-    double* du2 = LU + (3 * (int64_t)n) * nvec + j;
-    double* pv = LU + (4 * (int64_t)n) * nvec + j;
-#define AT(p, i) (p)[(int64_t)(i) * nvec]
-    const double lm = lam[j];
+// inverse iteration, one thread per wanted vector. The pivoted LU of (Tri - lambda I) is
+// computed with the running pivot row kept in registers and written out once to LDS; the
+// solves stream through it. Column j of Z (row-major, stride nvec) receives vector j.
+// Launch: ceil(nvec / INV_VPW) workgroups of 64 threads, 2 n + INV_VPW (6 n + 4) doubles of LDS.
+constexpr int INV_VPW = 4;
+__global__ __launch_bounds__(64) void inviter_kernel(const double* __restrict__ de, const double* __restrict__ theta,
+                                                     int n, int nvec, double* __restrict__ Z) {
+  extern __shared__ double lds[];
+  const int tid = threadIdx.x;
+  double* d = lds;
+  double* e = lds + n;
+  for (int i = tid; i < n; i += blockDim.x) {
+    d[i] = de[i];
+    e[i] = de[n + i];
+  }
+  const double tnorm = de[3 * n + 2];
+  __syncthreads();
+  {
+    const int jl = tid;
+    const int j = blockIdx.x * INV_VPW + jl;
+    if (jl >= INV_VPW || j >= nvec) return;
+    double* dl = lds + 2 * n + (int64_t)jl * (6 * n + 4);  // padded against bank conflicts
+    double* dd = dl + n;
+    double* du = dd + n;
+    double* du2 = du + n;
+    double* pv = du2 + n;
+    double* zl = pv + n;
+#define AT(p, i) (p)[(i)]
+    const double lm = theta[j];
     const double tiny = DBL_EPSILON * tnorm;
     // running values of the current pivot row: a = dd[i], u1 = du[i]
     double a = d[0] - lm, u1 = e[0];
@@ -311,7 +350,7 @@ __global__ __launch_bounds__(EIG_THREADS) void symeig_kernel(const double* __res
     AT(dd, n - 1) = a;
     AT(du, n - 1) = 0.0;
     AT(du2, n - 1) = 0.0;
-    double* z = Z + j;  // column j of Z, stride nvec
+    double* z = zl;
     uint64_t h = mix64(0x5D0C5EEDull + (uint64_t)j * 1315423911ull);
     for (int i = 0; i < n; i++) {
       h = mix64(h + i);
@@ -346,12 +385,20 @@ __global__ __launch_bounds__(EIG_THREADS) void symeig_kernel(const double* __res
       for (int i = 0; i < n; i++) AT(z, i) *= nr;
     }
 #undef AT
+    for (int i = 0; i < n; i++) Z[(int64_t)i * nvec + j] = zl[i];
   }
-  __syncthreads();
-  // Cholesky QR, twice, of Z (n x nvec, row-major), when orthonormal vectors are needed
-  // (restarts, final vectors). G = Z^T Z from row chunks of Z staged in LDS.
+}
+
+// Cholesky QR, twice, of Z (n x nvec, row-major), when orthonormal vectors are needed
+// (restarts, final vectors). G = Z^T Z from row chunks of Z staged in LDS. One workgroup.
+__global__ __launch_bounds__(EIG_THREADS) void cholqr_kernel(int n, int nvec, double* __restrict__ Z,
+                                                             double* __restrict__ LU) {
+  __shared__ double big[EIG_BIG];
+  __shared__ double red[32];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nwave = nthr >> 6;
   double* G = LU;  // nvec x nvec (upper triangle)
-  for (int pass = 0; pass < 2 && orth && nvec > 1; pass++) {
+  for (int pass = 0; pass < 2; pass++) {
     const int nt = (nvec + 3) / 4;
     const int RC = min(n, EIG_BIG / nvec);
     for (int t0 = 0; t0 < nt * nt; t0 += nthr) {
@@ -438,15 +485,23 @@ __global__ __launch_bounds__(EIG_THREADS) void symeig_kernel(const double* __res
       __syncthreads();
     }
   }
+}
 
-  // ---- 4. back-transformation U = H_0 H_1 ... H_{n-3} Z (reflectors applied last to first):
-  // blocks of 16 columns in LDS, one wave per column; nr reflectors at a time are staged in
-  // LDS (zero-padded to full length) between barriers.
+// back-transformation U = H_0 H_1 ... H_{n-3} Z (reflectors applied last to first): one
+// workgroup per block of 16 columns, held in LDS, one wave per column; nr reflectors at a
+// time are staged in LDS (zero-padded to full length) between barriers.
+__global__ __launch_bounds__(EIG_THREADS) void backtr_kernel(const double* __restrict__ A, int n, int nvec,
+                                                             const double* __restrict__ Z, double* __restrict__ U,
+                                                             int ldu) {
+  __shared__ double big[EIG_BIG];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6;
   {
     double* zs = big;
     double* vb = big + 16 * n;
     const int nr = max(1, min(16, (EIG_BIG - 16 * n) / n));
-    for (int cb = 0; cb < nvec; cb += 16) {
+    {
+      const int cb = 16 * blockIdx.x;
       const int ncol = min(16, nvec - cb);
       for (int q = tid; q < n * ncol; q += nthr) {
         const int i = q / ncol, c = q - (q / ncol) * ncol;
@@ -486,9 +541,20 @@ void symeig(const double* T, int ldt, int n, int nvec, double* theta, double* U,
   TRBL_REQUIRE(n >= 1 && n <= EIG_NMAX && nvec >= 1 && nvec <= n, TRBL_E_INVALID, "eigensolver size out of range");
   w.a.alloc((size_t)n * n * sizeof(double));
   w.z.alloc((size_t)n * nvec * sizeof(double));
-  w.lu.alloc((size_t)std::max(5 * n * nvec, nvec * nvec) * sizeof(double));
-  hipLaunchKernelGGL(symeig_kernel, dim3(1), dim3(EIG_THREADS), 0, st, T, ldt, n, nvec, orth ? 1 : 0, theta, U, ldu,
-                     w.a.as<double>(), w.z.as<double>(), w.lu.as<double>());
+  w.lu.alloc((size_t)nvec * nvec * sizeof(double));
+  w.aux.alloc((size_t)(3 * n + 4) * sizeof(double));
+  double* de = w.aux.as<double>();
+  hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(EIG_THREADS), 0, st, T, ldt, n, w.a.as<double>(), de);
+  const int nwant = nvec < n ? nvec + 1 : nvec;
+  hipLaunchKernelGGL(bisect_kernel, dim3((nwant * BIS_TPE + 255) / 256), dim3(256), 0, st, de, n, nvec, theta);
+  hipLaunchKernelGGL(inviter_kernel, dim3((nvec + INV_VPW - 1) / INV_VPW), dim3(64),
+                     (size_t)(2 * n + INV_VPW * (6 * n + 4)) * sizeof(double), st, de, theta, n, nvec,
+                     w.z.as<double>());
+  if (orth && nvec > 1)
+    hipLaunchKernelGGL(cholqr_kernel, dim3(1), dim3(EIG_THREADS), 0, st, n, nvec, w.z.as<double>(),
+                       w.lu.as<double>());
+  hipLaunchKernelGGL(backtr_kernel, dim3((nvec + 15) / 16), dim3(EIG_THREADS), 0, st, w.a.as<double>(), n, nvec,
+                     w.z.as<double>(), U, ldu);
   TRBL_HIP(hipGetLastError());
 }
 
