@@ -14,6 +14,8 @@
 // written for this library.
 #include <cfloat>
 
+#include <hip/hip_cooperative_groups.h>
+
 #include "dense.h"
 
 namespace trbl {
@@ -62,127 +64,98 @@ __device__ static int sturm(const double* d, const double* e2, int n, double x, 
 
 constexpr int EIG_BIG = 20 * EIG_NMAX;  // shared work area (doubles)
 
-// tridiagonal (d, e, e2) and the bisection interval: de[0..n) = d, de[n..2n) = e,
-// de[2n..3n) = e^2, de[3n..3n+4) = (lower bound, upper bound, norm bound, pivmin)
-__global__ __launch_bounds__(EIG_THREADS) void tridiag_kernel(const double* __restrict__ T, int ldt, int n,
-                                                              double* __restrict__ A, double* __restrict__ de) {
-  __shared__ double big[2 * PNB * EIG_NMAX];
-  double(*Vp)[EIG_NMAX] = reinterpret_cast<double(*)[EIG_NMAX]>(big);
-  double(*Wp)[EIG_NMAX] = reinterpret_cast<double(*)[EIG_NMAX]>(big + PNB * EIG_NMAX);
-  __shared__ double d[EIG_NMAX], e[EIG_NMAX], e2[EIG_NMAX], vv[EIG_NMAX], pw[EIG_NMAX];
-  __shared__ double part[EIG_THREADS];
-  __shared__ double red[32], wlo[16], whi[16], wnm[16], xw[PNB], yv[PNB];
+// Householder reduction to tridiagonal form, unblocked, on ceil(n / TRI_RW) cooperating
+// workgroups of 256 threads. Workgroup g holds rows [g TRI_RW, (g+1) TRI_RW) of the current
+// matrix in LDS. Step j (reflector H_j = I - 2 v v^T, |v| = 1, acting on rows j+1..n-1):
+// every workgroup forms v from row j (which it holds: see below), computes p = A v on its own
+// rows and publishes them, and the owner of row j+1 publishes that row as it stands before
+// step j; after one grid barrier every workgroup forms w = 2p - 2 (v^T p) v, applies
+// A <- A - v w^T - w v^T to its rows and to its copy of row j+1, the next step's row. The
+// exchange area alternates between two halves, so one barrier per step suffices: a half is
+// rewritten only after every workgroup has passed the barrier that follows its last read.
+// Reflector j is kept in row j of A. Output: de[0..n) = d, de[n..2n) = e, de[2n..3n) = e^2,
+// de[3n..3n+4) = (lower bound, upper bound, norm bound, pivmin) of the spectrum.
+constexpr int TRI_RW = 16;
+__global__ __launch_bounds__(256) void tridiag_kernel(const double* __restrict__ T, int ldt, int n,
+                                                      double* __restrict__ A, double* __restrict__ de,
+                                                      double* __restrict__ xb) {
+  extern __shared__ double lds[];
+  __shared__ double d[EIG_NMAX], e[EIG_NMAX], e2[EIG_NMAX];
+  __shared__ double red[32], wlo[16], whi[16], wnm[16];
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6, nwave = nthr >> 6;
-
-  for (int r = wave; r < n; r += nwave)
-    for (int c = lane; c < n; c += 64) A[(int64_t)r * n + c] = T[(int64_t)r * ldt + c];
+  const int g = blockIdx.x, r0 = g * TRI_RW, nr = min(TRI_RW, n - r0);
+  double* Ar = lds;              // nr x n, own rows
+  double* v = Ar + TRI_RW * n;   // reflector
+  double* w = v + n;             // 2p - 2 (v^T p) v
+  double* x = w + n;             // row j of the current matrix
+  const int row = tid >> 4, sub = tid & 15;  // p and the update: 16 lanes per own row
+  for (int q = tid; q < nr * n; q += nthr) Ar[q] = T[(int64_t)(r0 + q / n) * ldt + q % n];
+  for (int c = tid; c < n; c += nthr) x[c] = T[c];
   __syncthreads();
-
-  // ---- 1. Householder tridiagonalisation, blocked in panels of PNB columns. Inside a panel
-  // the trailing matrix is not updated; its product with v is corrected by the panel's
-  // earlier (v_t, w_t) pairs, A_cur = A_panel_start - sum_t (v_t w_t^T + w_t v_t^T). After the
-  // panel the trailing block receives the rank-2*PNB update at once. Reflector j (H_j =
-  // I - 2 v v^T, |v| = 1, acting on rows j+1..n-1) is kept in row j of A.
-  for (int k0 = 0; k0 + 2 < n; k0 += PNB) {
-    const int nbp = min(PNB, n - 2 - k0);
-    for (int i = 0; i < nbp; i++) {
-      const int j = k0 + i;
-      const int len = n - j - 1;
-      // column j (rows j..n-1) of the current matrix
-      for (int r = tid; r <= len; r += nthr) {
-        const int rr = j + r;
-        double a = A[(int64_t)j * n + rr];
-        for (int t = 0; t < i; t++) a -= Vp[t][rr] * Wp[t][j] + Wp[t][rr] * Vp[t][j];
-        vv[r] = a;
-      }
-      __syncthreads();
-      double s = 0.0;
-      for (int r = tid; r < len; r += nthr) s += vv[1 + r] * vv[1 + r];
-      const double s2 = block_sum(s, red);
-      const double x0 = vv[1];
-      const double sigma = sqrt(s2);
-      if (tid == 0) d[j] = vv[0];
-      if (sigma == 0.0) {
-        for (int r = tid; r < n; r += nthr) {
-          Vp[i][r] = 0.0;
-          Wp[i][r] = 0.0;
-          if (r > j) A[(int64_t)j * n + r] = 0.0;
-        }
-        if (tid == 0) e[j] = 0.0;
-        __syncthreads();
-        continue;
-      }
+  for (int j = 0; j + 2 < n; j++) {
+    double* xh = xb + (int64_t)(j & 1) * 2 * n;  // [0, n): p; [n, 2n): row j+1
+    double s = 0.0;
+    for (int c = j + 1 + tid; c < n; c += nthr) s += x[c] * x[c];
+    const double s2 = block_sum(s, red);
+    const double x0 = x[j + 1];
+    const double sigma = sqrt(s2);
+    if (tid == 0) d[j] = x[j];
+    if (sigma == 0.0) {
+      for (int c = tid; c < n; c += nthr) v[c] = 0.0;
+      if (tid == 0) e[j] = 0.0;
+    } else {
       const double alpha = (x0 > 0.0) ? -sigma : sigma;
       const double vn = sqrt(s2 - x0 * x0 + (x0 - alpha) * (x0 - alpha));
-      for (int r = tid; r < n; r += nthr) Vp[i][r] = r <= j ? 0.0 : (r == j + 1 ? x0 - alpha : vv[r - j]) / vn;
+      for (int c = tid; c < n; c += nthr) v[c] = c <= j ? 0.0 : (c == j + 1 ? x0 - alpha : x[c]) / vn;
       if (tid == 0) e[j] = alpha;
-      __syncthreads();
-      // p = A_panel_start[j+1:, j+1:] v. A is symmetric, so p[c] = sum_r A[r][c] v[r]: a thread
-      // owns column c (coalesced row reads) and the rows are split over ng groups whose partial
-      // sums meet in LDS. Then the dots of the earlier panel vectors with v.
-      const double* vi = &Vp[i][j + 1];
-      const int cp = (len + 63) & ~63;
-      const int ng = max(1, nthr / cp);
-      {
-        const int g = tid / cp, c = tid - (tid / cp) * cp;
-        if (g < ng && c < len) {
-          const double* ac = A + (int64_t)(j + 1) * n + j + 1 + c;
-          double t = 0.0;
-#pragma unroll 8
-          for (int r = g; r < len; r += ng) t += ac[(int64_t)r * n] * vi[r];
-          part[g * cp + c] = t;
-        }
-      }
-      for (int q = wave; q < 2 * i; q += nwave) {
-        const double* u = (q < i) ? &Wp[q][j + 1] : &Vp[q - i][j + 1];
-        double t = 0.0;
-        for (int c = lane; c < len; c += 64) t += u[c] * vi[c];
-        t = wave_sum(t);
-        if (lane == 0) (q < i ? xw[q] : yv[q - i]) = t;
-      }
-      __syncthreads();
-      double kp = 0.0;
-      for (int r = tid; r < len; r += nthr) {
-        const int rr = j + 1 + r;
-        double p = 0.0;
-        for (int g = 0; g < ng; g++) p += part[g * cp + r];
-        for (int t = 0; t < i; t++) p -= Vp[t][rr] * xw[t] + Wp[t][rr] * yv[t];
-        pw[r] = p;
-        kp += vi[r] * p;
-      }
-      const double K = block_sum(kp, red);
-      for (int r = tid; r < n; r += nthr) {
-        Wp[i][r] = r <= j ? 0.0 : 2.0 * pw[r - j - 1] - 2.0 * K * Vp[i][r];
-        if (r > j) A[(int64_t)j * n + r] = Vp[i][r];
-      }
-      __syncthreads();
     }
-    // trailing update of rows / columns >= k0 + nbp
-    const int s0 = k0 + nbp;
-    for (int r = s0 + wave; r < n; r += nwave) {
-      double vr[PNB], wr[PNB];
-#pragma unroll
-      for (int t = 0; t < PNB; t++) {
-        vr[t] = t < nbp ? Vp[t][r] : 0.0;
-        wr[t] = t < nbp ? Wp[t][r] : 0.0;
-      }
-      double* ar = A + (int64_t)r * n;
-      for (int c = s0 + lane; c < n; c += 64) {
-        double a = ar[c];
-#pragma unroll
-        for (int t = 0; t < PNB; t++) a -= vr[t] * Wp[t][c] + wr[t] * Vp[t][c];
-        ar[c] = a;
-      }
+    __syncthreads();
+    if (g == 0)
+      for (int c = j + 1 + tid; c < n; c += nthr) A[(int64_t)j * n + c] = v[c];
+    const int r = r0 + row;
+    if (row < nr && r > j) {
+      const double* ar = Ar + row * n;
+      double t = 0.0;
+      for (int c = j + 1 + sub; c < n; c += 16) t += ar[c] * v[c];
+      for (int o = 8; o > 0; o >>= 1) t += __shfl_xor(t, o, 16);
+      if (sub == 0) xh[r] = t;
+    }
+    if (j + 1 >= r0 && j + 1 < r0 + nr)
+      for (int c = j + 1 + tid; c < n; c += nthr) xh[n + c] = Ar[(j + 1 - r0) * n + c];
+    grid.sync();
+    double kp = 0.0;
+    for (int c = j + 1 + tid; c < n; c += nthr) {
+      const double pc = xh[c];
+      w[c] = pc;
+      kp += v[c] * pc;
+    }
+    const double K = block_sum(kp, red);
+    for (int c = j + 1 + tid; c < n; c += nthr) w[c] = 2.0 * w[c] - 2.0 * K * v[c];
+    __syncthreads();
+    if (row < nr && r > j) {
+      double* ar = Ar + row * n;
+      const double vr = v[r], wr = w[r];
+      for (int c = j + 1 + sub; c < n; c += 16) ar[c] -= vr * w[c] + wr * v[c];
+    }
+    {
+      const double vj = v[j + 1], wj = w[j + 1];
+      for (int c = j + 1 + tid; c < n; c += nthr) x[c] = xh[n + c] - (vj * w[c] + wj * v[c]);
     }
     __syncthreads();
   }
+  // the last two rows: row n-2 is in x; the diagonal of row n-1 comes from its owner
+  double* xl = xb + 4 * (int64_t)n;
+  if (tid == 0 && n - 1 >= r0 && n - 1 < r0 + nr) xl[0] = Ar[(n - 1 - r0) * n + n - 1];
+  grid.sync();
+  if (g != 0) return;
   if (tid == 0) {
     if (n >= 2) {
-      d[n - 2] = A[(int64_t)(n - 2) * n + n - 2];
-      e[n - 2] = A[(int64_t)(n - 1) * n + n - 2];
+      d[n - 2] = x[n - 2];
+      e[n - 2] = x[n - 1];
     }
-    d[n - 1] = A[(int64_t)(n - 1) * n + n - 1];
+    d[n - 1] = xl[0];
     e[n - 1] = 0.0;
   }
   __syncthreads();
@@ -230,6 +203,7 @@ __global__ __launch_bounds__(EIG_THREADS) void tridiag_kernel(const double* __re
     de[3 * n + 3] = pivmin;
   }
 }
+
 
 // eigenvalues by multisection: a group of BIS_TPE threads refines one eigenvalue (the nvec
 // lowest and the largest); each round its threads take Sturm counts at BIS_TPE interior points
@@ -543,8 +517,16 @@ void symeig(const double* T, int ldt, int n, int nvec, double* theta, double* U,
   w.z.alloc((size_t)n * nvec * sizeof(double));
   w.lu.alloc((size_t)nvec * nvec * sizeof(double));
   w.aux.alloc((size_t)(3 * n + 4) * sizeof(double));
+  w.xb.alloc((size_t)(4 * n + 8) * sizeof(double));
   double* de = w.aux.as<double>();
-  hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(EIG_THREADS), 0, st, T, ldt, n, w.a.as<double>(), de);
+  {
+    double* A = w.a.as<double>();
+    double* xb = w.xb.as<double>();
+    void* args[] = {(void*)&T, (void*)&ldt, (void*)&n, (void*)&A, (void*)&de, (void*)&xb};
+    const size_t shm = (size_t)(TRI_RW + 3) * n * sizeof(double);
+    TRBL_HIP(hipLaunchCooperativeKernel((const void*)tridiag_kernel, dim3((n + TRI_RW - 1) / TRI_RW), dim3(256), args,
+                                        (unsigned)shm, st));
+  }
   const int nwant = nvec < n ? nvec + 1 : nvec;
   hipLaunchKernelGGL(bisect_kernel, dim3((nwant * BIS_TPE + 255) / 256), dim3(256), 0, st, de, n, nvec, theta);
   hipLaunchKernelGGL(inviter_kernel, dim3((nvec + INV_VPW - 1) / INV_VPW), dim3(64),
