@@ -563,14 +563,34 @@ template <class TA, class TY, int NT>
 __global__ __launch_bounds__(512) void rowgemm_kernel(const TA* A, int64_t lda, int m, const double* __restrict__ U,
                                                       int64_t ldu, int ncol, TY* Y, int64_t ldy, int64_t D, int vsrc,
                                                       int vdst, int nv) {
-  constexpr int WAVES = 8, ROWS = WAVES * 16, KC = 16;
+  // U is staged by chunks of KC rows into two alternating LDS buffers and A is loaded one
+  // chunk ahead in registers, so each chunk costs one barrier and its loads overlap the
+  // previous chunk's MFMAs
+  constexpr int WAVES = 8, ROWS = WAVES * 16, KC = 16, UW = NT * 16;
+  constexpr int UPT = (KC * UW + WAVES * 64 - 1) / (WAVES * 64);  // U values per thread and chunk
   extern __shared__ double lds[];
-  double* Us = lds;                      // KC x (NT*16)
-  double* Vs = lds + KC * NT * 16;       // ROWS x nv (copy of the moved block)
+  double* Us = lds;                 // 2 x KC x UW
+  double* Vs = lds + 2 * KC * UW;   // ROWS x nv (copy of the moved block)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int ctile = (ncol + 15) >> 4;
+  const int nk = (m + KC - 1) / KC;
   const int64_t ntiles = (D + ROWS - 1) / ROWS;
+  auto load_u = [&](int k0, double (&u)[UPT]) {
+#pragma unroll
+    for (int i = 0; i < UPT; i++) {
+      const int e = threadIdx.x + i * WAVES * 64;
+      const int k = k0 + e / UW, c = e % UW;
+      u[i] = (e < KC * UW && k < m && c < ncol) ? U[k * ldu + c] : 0.0;
+    }
+  };
+  auto store_u = [&](int buf, const double (&u)[UPT]) {
+#pragma unroll
+    for (int i = 0; i < UPT; i++) {
+      const int e = threadIdx.x + i * WAVES * 64;
+      if (e < KC * UW) Us[buf * KC * UW + e] = u[i];
+    }
+  };
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t rbase = tile * ROWS;
     if (vsrc >= 0) {
@@ -583,25 +603,35 @@ __global__ __launch_bounds__(512) void rowgemm_kernel(const TA* A, int64_t lda, 
 #pragma unroll
     for (int q = 0; q < NT; q++) acc[q] = d4{0, 0, 0, 0};
     const int64_t ra = rbase + wave * 16 + li;
-    for (int k0 = 0; k0 < m; k0 += KC) {
-      __syncthreads();
-      for (int e = threadIdx.x; e < KC * NT * 16; e += blockDim.x) {
-        const int k = k0 + e / (NT * 16), c = e % (NT * 16);
-        Us[e] = (k < m && c < ncol) ? U[k * ldu + c] : 0.0;
-      }
-      __syncthreads();
-      const int kk = 4 * lk;
-      double a4[4];
-      if (ra < D) ld4(A + ra * lda + k0 + kk, m - (k0 + kk), a4);
+    const int kk = 4 * lk;
+    auto load_a = [&](int k0, double (&a4)[4]) {
+      if (ra < D && k0 + kk < m) ld4(A + ra * lda + k0 + kk, m - (k0 + kk), a4);
       else a4[0] = a4[1] = a4[2] = a4[3] = 0.0;
+    };
+    double u[UPT], a4[4], an[4];
+    load_u(0, u);
+    store_u(0, u);
+    load_a(0, a4);
+    __syncthreads();
+    for (int s = 0; s < nk; s++) {
+      const int k0 = s * KC, buf = s & 1;
+      const bool more = s + 1 < nk;
+      if (more) {
+        load_u(k0 + KC, u);
+        load_a(k0 + KC, an);
+      }
+      const double* ub = Us + buf * KC * UW;
 #pragma unroll
       for (int t = 0; t < 4; t++) {
 #pragma unroll
         for (int q = 0; q < NT; q++)
-          if (q < ctile) acc[q] = mfma(a4[t], Us[(kk + t) * NT * 16 + q * 16 + li], acc[q]);
+          if (q < ctile) acc[q] = mfma(a4[t], ub[(kk + t) * UW + q * 16 + li], acc[q]);
       }
+      if (more) store_u(buf ^ 1, u);
+      __syncthreads();  // the last one also orders every read of the tile's A before the writes of Y
+#pragma unroll
+      for (int t = 0; t < 4; t++) a4[t] = an[t];
     }
-    __syncthreads();  // all waves of the tile have finished reading A before anyone writes Y
 #pragma unroll
     for (int q = 0; q < NT; q++) {
       if (q >= ctile) continue;
@@ -828,7 +858,7 @@ void rowgemm(const TA* A, int64_t lda, int m, const double* U, int64_t ldu, int 
              int vsrc, int vdst, int nv, hipStream_t st) {
   const int G = grid_for(D, 128, 2048);
   const int nt = (ncol + 15) / 16;
-  auto shm = [&](int NT) { return (size_t)(16 * NT * 16 + 128 * std::max(nv, 1)) * sizeof(double); };
+  auto shm = [&](int NT) { return (size_t)(2 * 16 * NT * 16 + 128 * std::max(nv, 1)) * sizeof(double); };
   if (nt <= 4)
     hipLaunchKernelGGL((rowgemm_kernel<TA, TY, 4>), dim3(G), dim3(512), shm(4), st, A, lda, m, U, ldu, ncol, Y, ldy,
                        D, vsrc, vdst, nv);
