@@ -41,6 +41,8 @@ void random_block(T* out, int64_t ld, int64_t D, int nb, uint64_t seed, hipStrea
 template <class TS, class TD>
 void copy_cols(const TS* src, int64_t lds_, TD* dst, int64_t ldd, int64_t D, int ncol, hipStream_t st);
 void t_alpha(double* T, int ldt, int c0, int nb, const double* C1, hipStream_t st);
+// C[r, :] = T[r, c0:c0+nb] for r in [r_lo, c0) (C row-major, nb columns)
+void t_column(const double* T, int ldt, int c0, int r_lo, int nb, double* C, hipStream_t st);
 void t_beta(double* T, int ldt, int c0, int m, int nb, const double* beta, hipStream_t st);
 void resid(const double* beta, int nb, const double* U, int ldu, int m, int n, double* rho, hipStream_t st);
 void t_restart(double* T, int ldt, int lm, const double* theta, int ls, const double* beta, int nb, const double* U,

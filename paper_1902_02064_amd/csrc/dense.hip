@@ -690,6 +690,14 @@ __global__ void t_alpha_kernel(double* T, int ldt, int c0, int nb, const double*
   T[(c0 + i) * ldt + c0 + j] = 0.5 * (C1[(c0 + i) * nb + j] + C1[(c0 + j) * nb + i]);
 }
 
+__global__ void t_column_kernel(const double* T, int ldt, int c0, int r_lo, int nb, double* C) {
+  // rows r_lo..c0-1 of column block c0 of T (the couplings of V_k to the earlier vectors)
+  const int e = threadIdx.x + blockIdx.x * blockDim.x;
+  if (e >= (c0 - r_lo) * nb) return;
+  const int r = r_lo + e / nb, c = e % nb;
+  C[r * nb + c] = T[r * ldt + c0 + c];
+}
+
 __global__ void t_beta_kernel(double* T, int ldt, int c0, int m, int nb, const double* beta) {
   const int e = threadIdx.x + blockIdx.x * blockDim.x;
   if (e >= nb * nb) return;
@@ -897,6 +905,11 @@ void copy_cols(const TS* src, int64_t lds_, TD* dst, int64_t ldd, int64_t D, int
 
 void t_alpha(double* T, int ldt, int c0, int nb, const double* C1, hipStream_t st) {
   hipLaunchKernelGGL(t_alpha_kernel, dim3((nb * nb + 255) / 256), dim3(256), 0, st, T, ldt, c0, nb, C1);
+}
+void t_column(const double* T, int ldt, int c0, int r_lo, int nb, double* C, hipStream_t st) {
+  if (c0 <= r_lo) return;
+  hipLaunchKernelGGL(t_column_kernel, dim3(((c0 - r_lo) * nb + 255) / 256), dim3(256), 0, st, T, ldt, c0, r_lo, nb, C);
+  TRBL_HIP(hipGetLastError());
 }
 void t_beta(double* T, int ldt, int c0, int m, int nb, const double* beta, hipStream_t st) {
   hipLaunchKernelGGL(t_beta_kernel, dim3((nb * nb + 255) / 256), dim3(256), 0, st, T, ldt, c0, m, nb, beta);

@@ -2,9 +2,10 @@
 //
 // Per block iteration k (all vector work on one HIP stream, all D-length data in HBM):
 //   W := H V_k                           on-the-fly block H.V (hv.hip)
-//   C1 := Q^T W,  alpha_k := sym(V_k^T W) (rows of C1 belonging to V_k)
+//   alpha_k := sym(V_k^T W)
 //   W -= Q C1 ; C2 := Q^T W ; W -= Q C2   classical Gram-Schmidt twice against every
-//                                         stored vector v_1 .. v_{k_x + p k}
+//                                         stored vector v_1 .. v_{k_x + p k}; C1 is the
+//                                         column block k of T (exact Q^T H V_k), C2 computed
 //   V_{k+1} beta_k := QR(W)               Cholesky QR, twice (beta = R2 R1, diag > 0)
 //   T blocks (k,k) = alpha_k, (k+1,k) = beta_k, (k,k+1) = beta_k^T
 //   diagonalise T^(k); rho_i = || beta_k U[last block rows, i] ||
@@ -203,16 +204,27 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
     void* Wh = mixed ? (void*)W32 : (void*)W;
     launch_apply(m, mixed ? TRBL_MIXED : TRBL_FP64, nb, Q + c0, ldq, Wh, nb, st);
     TRBL_HIP(hipEventRecord(ev.e[1], st));
-    // projections and block classical Gram-Schmidt, twice
+    // alpha_k = V_k^T W, then block classical Gram-Schmidt twice against all stored vectors.
+    // The first pass takes its coefficients from T: in exact arithmetic Q^T H V_k is the
+    // column block k of T (alpha_k, beta_{k-1}^T and, right after a restart, the coupling
+    // to the Ritz vectors), so only those vectors are read; what that misses is of the
+    // order of the rounding of a computed first pass, and the full second pass removes it.
+    const int r_lo = k == 1 ? 0 : c0 - nb;
     if (mixed) {
-      tn<float, float>((const float*)Q, ldq, mcur, W32, nb, nb, D, C1, sc, st);
+      tn<float, float>((const float*)Q + c0, ldq, nb, W32, nb, nb, D, C1 + (size_t)c0 * nb, sc, st);
       t_alpha(T, lm, c0, nb, C1, st);
-      update<float, float>((const float*)Q, ldq, mcur, C1, W32, nb, W, nb, nb, D, 1, C2, sc, st);
+      t_column(T, lm, c0, r_lo, nb, C1, st);
+      update<float, float>((const float*)Q + r_lo, ldq, mcur - r_lo, C1 + (size_t)r_lo * nb, W32, nb, W, nb, nb, D,
+                           0, nullptr, sc, st);
+      tn<float, double>((const float*)Q, ldq, mcur, W, nb, nb, D, C2, sc, st);
       update<float, double>((const float*)Q, ldq, mcur, C2, W, nb, W, nb, nb, D, 2, nullptr, sc, st);
     } else {
-      tn<double, double>((const double*)Q, ldq, mcur, W, nb, nb, D, C1, sc, st);
+      tn<double, double>((const double*)Q + c0, ldq, nb, W, nb, nb, D, C1 + (size_t)c0 * nb, sc, st);
       t_alpha(T, lm, c0, nb, C1, st);
-      update<double, double>((const double*)Q, ldq, mcur, C1, W, nb, W, nb, nb, D, 1, C2, sc, st);
+      t_column(T, lm, c0, r_lo, nb, C1, st);
+      update<double, double>((const double*)Q + r_lo, ldq, mcur - r_lo, C1 + (size_t)r_lo * nb, W, nb, W, nb, nb, D,
+                             0, nullptr, sc, st);
+      tn<double, double>((const double*)Q, ldq, mcur, W, nb, nb, D, C2, sc, st);
       update<double, double>((const double*)Q, ldq, mcur, C2, W, nb, W, nb, nb, D, 2, nullptr, sc, st);
     }
     TRBL_HIP(hipEventRecord(ev.e[2], st));
