@@ -68,8 +68,9 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
 
   const int64_t ldq = round4(lm);
   const int ldu = std::max(ls, neig);
-  DevBuf Qb, Wb, W32b, Tb, C1b, C2b, Rb, thb, Ub, rhob, stb;
+  DevBuf Qb, Vkb, Wb, W32b, Tb, C1b, C2b, Rb, thb, Ub, rhob, stb;
   Qb.alloc((size_t)D * ldq * sizeof(TQ));
+  Vkb.alloc((size_t)D * nb * sizeof(TQ));
   Wb.alloc((size_t)D * nb * sizeof(double));
   if (mixed) W32b.alloc((size_t)D * nb * sizeof(float));
   Tb.alloc((size_t)lm * lm * sizeof(double));
@@ -81,6 +82,7 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
   rhob.alloc((size_t)std::max(neig, 64) * sizeof(double));
   stb.alloc(4 * sizeof(int));
   TQ* Q = Qb.as<TQ>();
+  TQ* Vk = Vkb.as<TQ>();  // packed copy of the current block: H.V stages whole source rows
   double* W = Wb.as<double>();
   float* W32 = W32b.as<float>();
   double* T = Tb.as<double>();
@@ -202,7 +204,8 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
     TRBL_HIP(hipEventRecord(ev.e[0], st));
     // W := H V_k
     void* Wh = mixed ? (void*)W32 : (void*)W;
-    launch_apply(m, mixed ? TRBL_MIXED : TRBL_FP64, nb, Q + c0, ldq, Wh, nb, st);
+    copy_cols<TQ, TQ>(Q + c0, ldq, Vk, nb, D, nb, st);
+    launch_apply(m, mixed ? TRBL_MIXED : TRBL_FP64, nb, Vk, nb, Wh, nb, st);
     TRBL_HIP(hipEventRecord(ev.e[1], st));
     // alpha_k = V_k^T W, then block classical Gram-Schmidt twice against all stored vectors.
     // The first pass takes its coefficients from T: in exact arithmetic Q^T H V_k is the
@@ -239,7 +242,7 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
     if (sth[0] || sth[1]) {
       // breakdown: W was scaled in place; form it again (same arithmetic) and take the
       // column-wise QR with replacement
-      launch_apply(m, mixed ? TRBL_MIXED : TRBL_FP64, nb, Q + c0, ldq, Wh, nb, st);
+      launch_apply(m, mixed ? TRBL_MIXED : TRBL_FP64, nb, Vk, nb, Wh, nb, st);
       if (mixed) {
         tn<float, float>((const float*)Q, ldq, mcur, W32, nb, nb, D, C1, sc, st);
         update<float, float>((const float*)Q, ldq, mcur, C1, W32, nb, W, nb, nb, D, 1, C2, sc, st);
