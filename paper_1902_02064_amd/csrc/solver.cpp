@@ -201,10 +201,10 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
     k++;
     const int c0 = kx + (k - 1) * nb;
     mcur = c0 + nb;
+    copy_cols<TQ, TQ>(Q + c0, ldq, Vk, nb, D, nb, st);
     TRBL_HIP(hipEventRecord(ev.e[0], st));
     // W := H V_k
     void* Wh = mixed ? (void*)W32 : (void*)W;
-    copy_cols<TQ, TQ>(Q + c0, ldq, Vk, nb, D, nb, st);
     launch_apply(m, mixed ? TRBL_MIXED : TRBL_FP64, nb, Vk, nb, Wh, nb, st);
     TRBL_HIP(hipEventRecord(ev.e[1], st));
     // alpha_k = V_k^T W, then block classical Gram-Schmidt twice against all stored vectors.
