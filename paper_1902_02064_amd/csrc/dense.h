@@ -51,7 +51,7 @@ void t_restart(double* T, int ldt, int lm, const double* theta, int ls, const do
 // Symmetric eigensolver of a small dense matrix (eig.hip): all eigenvalues ascending in theta[0:n],
 // orthonormal eigenvectors of the nvec lowest in U (n x nvec, ld ldu).
 struct EigWork {
-  DevBuf a, z, lu, aux, xb;
+  DevBuf a, z, lu, aux, xb, flag;
 };
 void symeig(const double* T, int ldt, int n, int nvec, double* theta, double* U, int ldu, EigWork& w, bool orth,
             hipStream_t st);

@@ -8,7 +8,8 @@
 //   3. eigenvectors of Tri by inverse iteration with a pivoted LU of (Tri - lambda I),
 //      one thread per vector with its LU in LDS, spread over workgroups;
 //   4. Cholesky QR (twice) of the vector block so that vectors of close eigenvalues are
-//      orthonormal (one workgroup, skipped when they already are);
+//      orthonormal (Gram tiles and the row solves spread over workgroups, the Cholesky
+//      factor on one; skipped when the vectors already are orthonormal);
 //   5. back-transformation U = Q Z, one workgroup per block of 16 columns.
 // Textbook methods (Householder; Sturm-sequence bisection; inverse iteration),
 // written for this library.
@@ -364,101 +365,101 @@ __global__ __launch_bounds__(64) void inviter_kernel(const double* __restrict__ 
 }
 
 // Cholesky QR, twice, of Z (n x nvec, row-major), when orthonormal vectors are needed
-// (restarts, final vectors). G = Z^T Z from row chunks of Z staged in LDS. One workgroup.
-__global__ __launch_bounds__(EIG_THREADS) void cholqr_kernel(int n, int nvec, double* __restrict__ Z,
-                                                             double* __restrict__ LU) {
-  __shared__ double big[EIG_BIG];
+// (restarts, final vectors). Each pass: G = Z^T Z (gram_kernel); if max |G - I| <= 64 eps the
+// vectors are already orthonormal to working accuracy (well separated eigenvalues) and the
+// flag `done` ends the procedure; otherwise the upper Cholesky factor R of G (chol_g_kernel)
+// and Z <- Z R^-1 (rsolve_kernel). Every kernel returns at once when `done` is set.
+typedef double d4e __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ d4e mfma_f64(double a, double b, d4e c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__global__ void clear_flag_kernel(int* f) { *f = 0; }
+
+// upper 16 x 16 tiles of G = Z^T Z, one wavefront per tile (MFMA f64 16x16x4 over 4 rows of Z)
+__global__ __launch_bounds__(64) void gram_kernel(const double* __restrict__ Z, int n, int nvec,
+                                                  double* __restrict__ G, const int* done) {
+  if (*done) return;
+  const int nt = (nvec + 15) / 16;
+  int t = blockIdx.x, rt = 0;
+  while (t >= nt - rt) {
+    t -= nt - rt;
+    rt++;
+  }
+  const int ct = rt + t;
+  const int li = threadIdx.x & 15, lk = threadIdx.x >> 4;
+  const int ca = rt * 16 + li, cb = ct * 16 + li;
+  d4e acc = {0, 0, 0, 0};
+  for (int i0 = 0; i0 < n; i0 += 4) {
+    const int i = i0 + lk;
+    const double x = (i < n && ca < nvec) ? Z[(int64_t)i * nvec + ca] : 0.0;
+    const double y = (i < n && cb < nvec) ? Z[(int64_t)i * nvec + cb] : 0.0;
+    acc = mfma_f64(x, y, acc);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; v++) {
+    const int r = rt * 16 + lk + 4 * v;
+    if (r < nvec && cb < nvec && cb >= r) G[(int64_t)r * nvec + cb] = acc[v];
+  }
+}
+
+// orthonormality test, then the upper Cholesky G = R^T R in place (row k finalised at step k)
+__global__ __launch_bounds__(EIG_THREADS) void chol_g_kernel(int nvec, double* __restrict__ G, int* done) {
   __shared__ double red[32];
+  if (*done) return;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6, nwave = nthr >> 6;
-  double* G = LU;  // nvec x nvec (upper triangle)
-  for (int pass = 0; pass < 2; pass++) {
-    const int nt = (nvec + 3) / 4;
-    const int RC = min(n, EIG_BIG / nvec);
-    for (int t0 = 0; t0 < nt * nt; t0 += nthr) {
-      const int tt = t0 + tid;
-      const int rt = tt / nt, ct = tt - (tt / nt) * nt;
-      const bool mine = tt < nt * nt && ct >= rt;
-      const int r0 = rt * 4, c0 = ct * 4;
-      double acc[4][4] = {};
-      for (int i0 = 0; i0 < n; i0 += RC) {
-        const int rc = min(RC, n - i0);
-        __syncthreads();
-        for (int q = tid; q < rc * nvec; q += nthr) big[q] = Z[(int64_t)i0 * nvec + q];
-        __syncthreads();
-        if (mine)
-          for (int i = 0; i < rc; i++) {
-            const double* zr = big + i * nvec;
-            double zl[4], zc[4];
-#pragma unroll
-            for (int q = 0; q < 4; q++) {
-              zl[q] = r0 + q < nvec ? zr[r0 + q] : 0.0;
-              zc[q] = c0 + q < nvec ? zr[c0 + q] : 0.0;
-            }
-#pragma unroll
-            for (int a = 0; a < 4; a++)
-#pragma unroll
-              for (int b = 0; b < 4; b++) acc[a][b] += zl[a] * zc[b];
-          }
-      }
-      if (mine)
-#pragma unroll
-        for (int a = 0; a < 4; a++)
-#pragma unroll
-          for (int b = 0; b < 4; b++)
-            if (r0 + a < nvec && c0 + b < nvec && c0 + b >= r0 + a) G[(int64_t)(r0 + a) * nvec + c0 + b] = acc[a][b];
+  double off = 0.0;
+  for (int r = wave; r < nvec; r += nwave)
+    for (int c = r + lane; c < nvec; c += 64) off = fmax(off, fabs(G[(int64_t)r * nvec + c] - (r == c ? 1.0 : 0.0)));
+  for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_xor(off, o, 64));
+  if (lane == 0) red[wave] = off;
+  __syncthreads();
+  off = 0.0;
+  for (int w = 0; w < nwave; w++) off = fmax(off, red[w]);
+  if (off <= 64.0 * DBL_EPSILON) {
+    if (tid == 0) *done = 1;
+    return;
+  }
+  for (int k = 0; k < nvec; k++) {
+    const double rkk = sqrt(fmax(G[(int64_t)k * nvec + k], 1e-300));
+    __syncthreads();
+    for (int c = k + 1 + tid; c < nvec; c += nthr) G[(int64_t)k * nvec + c] /= rkk;
+    if (tid == 0) G[(int64_t)k * nvec + k] = rkk;
+    __syncthreads();
+    for (int r = k + 1 + wave; r < nvec; r += nwave) {
+      const double gkr = G[(int64_t)k * nvec + r];
+      for (int c = r + lane; c < nvec; c += 64) G[(int64_t)r * nvec + c] -= gkr * G[(int64_t)k * nvec + c];
     }
     __syncthreads();
-    {  // already orthonormal to working accuracy (well separated eigenvalues): nothing to do
-      double off = 0.0;
-      for (int r = wave; r < nvec; r += nwave)
-        for (int c = r + lane; c < nvec; c += 64) off = fmax(off, fabs(G[(int64_t)r * nvec + c] - (r == c ? 1.0 : 0.0)));
-      for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_xor(off, o, 64));
-      if (lane == 0) red[wave] = off;
-      __syncthreads();
-      off = 0.0;
-      for (int w = 0; w < nwave; w++) off = fmax(off, red[w]);
-      __syncthreads();
-      if (off <= 64.0 * DBL_EPSILON) break;
-    }
-    // upper Cholesky G = R^T R in place (row k finalised at step k)
-    for (int k = 0; k < nvec; k++) {
-      const double rkk = sqrt(fmax(G[(int64_t)k * nvec + k], 1e-300));
-      __syncthreads();
-      for (int c = k + 1 + tid; c < nvec; c += nthr) G[(int64_t)k * nvec + c] /= rkk;
-      if (tid == 0) G[(int64_t)k * nvec + k] = rkk;
-      __syncthreads();
-      for (int r = k + 1 + wave; r < nvec; r += nwave) {
-        const double gkr = G[(int64_t)k * nvec + r];
-        for (int c = r + lane; c < nvec; c += 64) G[(int64_t)r * nvec + c] -= gkr * G[(int64_t)k * nvec + c];
-      }
-      __syncthreads();
-    }
-    // Z <- Z R^-1 by chunks of 64 rows in LDS; 16 lanes of one wave share a row: x R = z is
-    // solved column by column, each dot split over the 16 lanes
-    const int RZ = min(nthr / 16, EIG_BIG / nvec);
-    for (int i0 = 0; i0 < n; i0 += RZ) {
-      const int rr = min(RZ, n - i0);
-      for (int q = tid; q < rr * nvec; q += nthr) big[q] = Z[(int64_t)i0 * nvec + q];
-      __syncthreads();
-      const int row = tid >> 4, sub = tid & 15;
-      if (row < rr) {
-        double* zr = big + row * nvec;
-        for (int c = 0; c < nvec; c++) {
-          double s = 0.0;
-          for (int r = sub; r < c; r += 16) s += zr[r] * G[(int64_t)r * nvec + c];
-          for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
-          const double val = (zr[c] - s) / G[(int64_t)c * nvec + c];
-          __builtin_amdgcn_wave_barrier();
-          if (sub == 0) zr[c] = val;
-          __builtin_amdgcn_wave_barrier();
-        }
-      }
-      __syncthreads();
-      for (int q = tid; q < rr * nvec; q += nthr) Z[(int64_t)i0 * nvec + q] = big[q];
-      __syncthreads();
+  }
+}
+
+// Z <- Z R^-1, 16 rows per workgroup: 16 lanes share a row (staged in LDS) and solve x R = z
+// column by column, each dot split over the 16 lanes
+__global__ __launch_bounds__(256) void rsolve_kernel(int n, int nvec, double* __restrict__ Z,
+                                                     const double* __restrict__ G, const int* done) {
+  __shared__ double zs[16 * EIG_NMAX];
+  if (*done) return;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int i0 = blockIdx.x * 16, rr = min(16, n - i0);
+  for (int q = tid; q < rr * nvec; q += nthr) zs[q] = Z[(int64_t)i0 * nvec + q];
+  __syncthreads();
+  const int row = tid >> 4, sub = tid & 15;
+  if (row < rr) {
+    double* zr = zs + row * nvec;
+    for (int c = 0; c < nvec; c++) {
+      double s = 0.0;
+      for (int r = sub; r < c; r += 16) s += zr[r] * G[(int64_t)r * nvec + c];
+      for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
+      const double val = (zr[c] - s) / G[(int64_t)c * nvec + c];
+      __builtin_amdgcn_wave_barrier();
+      if (sub == 0) zr[c] = val;
+      __builtin_amdgcn_wave_barrier();
     }
   }
+  __syncthreads();
+  for (int q = tid; q < rr * nvec; q += nthr) Z[(int64_t)i0 * nvec + q] = zs[q];
 }
 
 // back-transformation U = H_0 H_1 ... H_{n-3} Z (reflectors applied last to first): one
@@ -518,6 +519,7 @@ void symeig(const double* T, int ldt, int n, int nvec, double* theta, double* U,
   w.lu.alloc((size_t)nvec * nvec * sizeof(double));
   w.aux.alloc((size_t)(3 * n + 4) * sizeof(double));
   w.xb.alloc((size_t)(4 * n + 8) * sizeof(double));
+  w.flag.alloc(sizeof(int));
   double* de = w.aux.as<double>();
   {
     double* A = w.a.as<double>();
@@ -532,9 +534,18 @@ void symeig(const double* T, int ldt, int n, int nvec, double* theta, double* U,
   hipLaunchKernelGGL(inviter_kernel, dim3((nvec + INV_VPW - 1) / INV_VPW), dim3(64),
                      (size_t)(2 * n + INV_VPW * (6 * n + 4)) * sizeof(double), st, de, theta, n, nvec,
                      w.z.as<double>());
-  if (orth && nvec > 1)
-    hipLaunchKernelGGL(cholqr_kernel, dim3(1), dim3(EIG_THREADS), 0, st, n, nvec, w.z.as<double>(),
-                       w.lu.as<double>());
+  if (orth && nvec > 1) {
+    int* done = w.flag.as<int>();
+    const int nt = (nvec + 15) / 16;
+    hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, st, done);
+    for (int pass = 0; pass < 2; pass++) {
+      hipLaunchKernelGGL(gram_kernel, dim3(nt * (nt + 1) / 2), dim3(64), 0, st, w.z.as<double>(), n, nvec,
+                         w.lu.as<double>(), done);
+      hipLaunchKernelGGL(chol_g_kernel, dim3(1), dim3(EIG_THREADS), 0, st, nvec, w.lu.as<double>(), done);
+      hipLaunchKernelGGL(rsolve_kernel, dim3((n + 15) / 16), dim3(256), 0, st, n, nvec, w.z.as<double>(),
+                         w.lu.as<double>(), done);
+    }
+  }
   hipLaunchKernelGGL(backtr_kernel, dim3((nvec + 15) / 16), dim3(EIG_THREADS), 0, st, w.a.as<double>(), n, nvec,
                      w.z.as<double>(), U, ldu);
   TRBL_HIP(hipGetLastError());
