@@ -103,6 +103,7 @@ static HVArgs<T> make_args(const Model& m, int nb, const void* V, int64_t ldv, v
   a.nblocks = (int)m.blocks.size();
   a.ncl = m.cl.nclass;
   a.tjmax = m.cl.tjmax;
+  a.nnum = m.n_neut <= MAXE ? m.n_neut : 0;
   a.nn_total = m.nn_total;
   // DMA staging needs 16-byte aligned chunks and full column tiles (set again once C is known)
   a.dma = ((uintptr_t)V % 16 == 0) && ((size_t)ldv * sizeof(T)) % 16 == 0;

@@ -34,6 +34,7 @@ struct HVArgs {
   T* W;
   int64_t ldv, ldw;
   int nb, ncl, tjmax, nblocks;
+  int nnum;              // neutron number operators merged in the diagonal class (0: none)
   int C, ntile, nchunk;  // column tile width, column tiles, target chunks per row/column
   int dma;               // source rows copied by global->LDS DMA (16-byte aligned rows)
   int64_t nn_total;
@@ -317,27 +318,49 @@ __global__ __launch_bounds__(NTB) void hv_rows_kernel(HVArgs<T> a) {
     if (nx.cls < ncl)
       stage_row(wr, ldu(a.blk_off, nx.sb) + (int64_t)nx.p * ldu(a.blk_dn, nx.sb), ldu(a.blk_dn, nx.sb));
     // hr points into LDS or into global memory: two copies of the loop keep every load
-    // typed (a generic pointer would make the compiler wait for the DMA in flight)
+    // typed (a generic pointer would make the compiler wait for the DMA in flight).
+    // Terms with the same source element are summed before the row is read: in the class of
+    // zero change of M and parity (the diagonal class) every neutron SD's first nnum jumps are
+    // its number operators (source n' itself), and a group of several proton jumps (the
+    // number operators, source p') shares every neutron entry.
+    const int nm = cur == 2 * a.tjmax ? a.nnum : 0;
     auto apply = [&](auto hrow) __attribute__((always_inline)) {
-      for (int j = it.jg; j < it.je; j++) {
-        const int pm = ldu(a.pj_meta, j);
-        const auto hr = hrow(j, pm);
-        const int ps = pm & 1;
+      auto body = [&](auto cf) __attribute__((always_inline)) {
 #pragma unroll
         for (int q = 0; q < MAXP; q++) {
+          if (nm > 0 && ec[q] >= nm) {
+            T sum = T(0);
+#pragma unroll
+            for (int i = 0; i < MAXE; i++)
+              if (i < nm) sum += cf(er[q][i]);
+            gather<T, C>(acc[q], sum, rd, er[q][0].x, rot);
+          }
 #pragma unroll
           for (int i = 0; i < MAXE; i++)
-            if (i < ec[q]) {
-              const int2 e = er[q][i];
-              const T hv = hr[e.y >> 1];
-              gather<T, C>(acc[q], ((e.y ^ ps) & 1) ? -hv : hv, rd, e.x, rot);
-            }
+            if (i >= nm && i < ec[q]) gather<T, C>(acc[q], cf(er[q][i]), rd, er[q][i].x, rot);
           for (int i = MAXE; i < ec[q]; i++) {
             const int2 e = a.nj_pack[eb[q] + i];
-            const T hv = hr[e.y >> 1];
-            gather<T, C>(acc[q], ((e.y ^ ps) & 1) ? -hv : hv, rd, e.x, rot);
+            gather<T, C>(acc[q], cf(e), rd, e.x, rot);
           }
         }
+      };
+      if (it.je - it.jg == 1) {
+        const int pm = ldu(a.pj_meta, it.jg);
+        const auto hr = hrow(it.jg, pm);
+        body([&](int2 e) __attribute__((always_inline)) {
+          const T hv = hr[e.y >> 1];
+          return ((e.y ^ pm) & 1) ? -hv : hv;
+        });
+      } else {
+        body([&](int2 e) __attribute__((always_inline)) {
+          T sum = T(0);
+          for (int j = it.jg; j < it.je; j++) {
+            const int pm = ldu(a.pj_meta, j);
+            const T hv = hrow(j, pm)[e.y >> 1];
+            sum += ((e.y ^ pm) & 1) ? -hv : hv;
+          }
+          return sum;
+        });
       }
     };
     if (hs_lds)

@@ -518,7 +518,8 @@ void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const
   m.dt.h_term.upload(hterm);
   // jump lists: from each SD g' remove x in g', add y not in g' \ {x} (y == x allowed).
   // Proton side: per (SD, class), sorted by source index so equal source rows are adjacent.
-  // Neutron side: class-major, so the lists of consecutive SDs in one class are contiguous.
+  // Neutron side: class-major, so the lists of consecutive SDs in one class are contiguous;
+  // each list has its number operators (source = the SD itself) first, then ascending sources.
   for (int s = 0; s < 2; s++) {
     const Species& S = m.sp[s];
     const std::vector<int>& oidx = s == 0 ? pop_idx : nop_idx;
@@ -542,7 +543,12 @@ void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const
           bucket[c].push_back({local, (oidx[x * ns + y] << 1) | (sy < 0 ? 1 : 0)});
         }
       }
-      for (auto& b : bucket) std::stable_sort(b.begin(), b.end(), [](auto& u, auto& v) { return u.first < v.first; });
+      const int own = (int)(g - S.sectors[S.sector_of[g]].start);
+      for (auto& b : bucket)
+        std::stable_sort(b.begin(), b.end(), [&](auto& u, auto& v) {
+          if (s == 1 && (u.first == own) != (v.first == own)) return u.first == own;
+          return u.first < v.first;
+        });
     }
     std::vector<int> start, jidx, jmeta;
     if (s == 0) {
