@@ -53,6 +53,87 @@ def species_sectors(orbits, n_part):
     return out
 
 
+def _orbit_subsets(orbits, o, k):
+    """Subsets of k m-states of orbit o as (bitmask, 2M), in ascending lexicographic order of
+    the state-index tuples (itertools.combinations order)."""
+    states = m_states(orbits)
+    idx = [s for s, (oo, _m) in enumerate(states) if oo == o]
+    out = []
+    for sub in itertools.combinations(idx, k):
+        out.append((sum(1 << s for s in sub), sum(states[s][1] for s in sub)))
+    return out
+
+
+def sector_words(orbits, n_part, twoM, parity):
+    """Words of one species sector (2M, parity) in Table-1 order, without visiting the other
+    sectors: for large spaces where ``species_sectors`` (all subsets) is too slow.
+
+    Same order as ``species_sectors``: partitions (occupation per orbit) in descending
+    lexicographic order; inside a partition the occupied-state tuples ascend
+    lexicographically, which is the nested order with orbit 0 outermost and each orbit's
+    subsets in combinations order. Subsets are combined orbit by orbit (numpy outer
+    products in that nested order), dropping partial words whose 2M can no longer reach
+    the target.
+    """
+    import numpy as np
+    norb = len(orbits)
+    caps = [tj + 1 for (_n, _l, tj) in orbits]
+
+    def mmax(o, k):  # largest 2M of k particles in orbit o
+        tj = orbits[o][2]
+        return sum(range(tj, tj - 2 * k, -2))
+
+    parts = []
+
+    def rec(o, left, cur):
+        if o == norb:
+            if left == 0:
+                parts.append(tuple(cur))
+            return
+        for k in range(min(caps[o], left), -1, -1):  # descending occupation first
+            rec(o + 1, left - k, cur + [k])
+
+    rec(0, n_part, [])
+    chunks = []
+    for part in parts:  # generated in descending lexicographic order
+        par = 1
+        for o, k in enumerate(part):
+            if orbits[o][1] % 2 and k % 2:
+                par = -par
+        if parity != 0 and par != parity:
+            continue
+        rest = [0] * (norb + 1)
+        for o in range(norb - 1, -1, -1):
+            rest[o] = rest[o + 1] + mmax(o, part[o])
+        words = np.zeros(1, dtype=np.uint64)
+        ms = np.zeros(1, dtype=np.int64)
+        for o, k in enumerate(part):
+            sub = _orbit_subsets(orbits, o, k)
+            sw = np.array([w for w, _ in sub], dtype=np.uint64)
+            sm = np.array([m for _, m in sub], dtype=np.int64)
+            words = (words[:, None] | sw[None, :]).ravel()
+            ms = (ms[:, None] + sm[None, :]).ravel()
+            keep = np.abs(twoM - ms) <= rest[o + 1]
+            words, ms = words[keep], ms[keep]
+        chunks.append(words[ms == twoM])
+    return np.concatenate(chunks) if chunks else np.zeros(0, dtype=np.uint64)
+
+
+def _sectors_for(orbits, n_part, n_other, twoM, parity):
+    """species_sectors(orbits, n_part), or for large species only the sectors that pair with
+    a sector of the other species (found from the counts) to total 2M and parity, listed by
+    ``sector_words`` (the partition entry is not filled in there)."""
+    from math import comb
+    if comb(len(m_states(orbits)), n_part) <= 2_000_000:
+        return species_sectors(orbits, n_part)
+    other = count_sds(orbits, n_other)
+    out = {}
+    for (tm, par), _c in sorted(count_sds(orbits, n_part).items()):
+        if any(tm + to == twoM and (parity == 0 or par * po == parity) for (to, po) in other):
+            out[(tm, par)] = [(int(w), None) for w in sector_words(orbits, n_part, tm, par)]
+    return out
+
+
 @dataclass
 class Block:
     twoMp: int
@@ -71,8 +152,8 @@ class ProductBasis:
         self.orbits = tuple(orbits)
         self.nstates = len(m_states(orbits))
         self.n_prot, self.n_neut, self.twoM, self.parity = n_prot, n_neut, twoM, parity
-        self.psec = species_sectors(orbits, n_prot)
-        self.nsec = species_sectors(orbits, n_neut)
+        self.psec = _sectors_for(orbits, n_prot, n_neut, twoM, parity)
+        self.nsec = _sectors_for(orbits, n_neut, n_prot, twoM, parity)
         keys = []
         for (tmp, pp) in self.psec:
             for (tmn, pn) in self.nsec:

@@ -5,7 +5,7 @@ import numpy as np
 
 import pytest
 
-from oracle.basis import ProductBasis, count_dim, count_sds, species_sectors
+from oracle.basis import ProductBasis, count_dim, count_sds, sector_words, species_sectors
 from workloads import PF_ORBITS, SD_ORBITS, SNSB_ORBITS, TABLE1_ORBITS, random_tbme
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
@@ -39,12 +39,36 @@ def test_printed_dimensions_dp(row):
     assert count_dim(o, z, o, n, 0, par) == dim
 
 
-@pytest.mark.parametrize("row", [r for r in _rows("dimensions.txt") if int(r[5]) < 3_000_000],
+@pytest.mark.parametrize("row", [r for r in _rows("dimensions.txt") if int(r[5]) < 10_000_000],
                          ids=lambda r: r[0])
 def test_printed_dimensions_enumerated(row):
     o = ORB[row[1]]
     b = ProductBasis(o, int(row[2]), int(row[3]), 0, int(row[4]))
     assert b.dim == int(row[5])
+
+
+def test_sector_words_matches_full_enumeration():
+    """The per-sector enumerator (used for large species) gives every sector of the full
+    subset enumeration in the same Table-1 order."""
+    for orbits, n in ((TABLE1_ORBITS, 3), (SD_ORBITS, 3), (PF_ORBITS, 4), (SNSB_ORBITS, 3), (SNSB_ORBITS, 4)):
+        for (tm, par), lst in species_sectors(orbits, n).items():
+            want = np.array([w for w, _ in lst], dtype=np.uint64)
+            assert np.array_equal(sector_words(orbits, n, tm, par), want), (n, tm, par)
+
+
+def test_sn112_words_are_the_sector():
+    """112Sn (Sec. 4.2): the enumerated positive-parity M = 0 sector has the printed dimension,
+    and every word is a distinct 12-neutron determinant with 2M = 0 and parity +."""
+    w = sector_words(SNSB_ORBITS, 12, 0, 1)
+    assert len(w) == 6210638
+    assert len(np.unique(w)) == len(w)
+    states = [(o, tm) for o, (_n, _l, tj) in enumerate(SNSB_ORBITS) for tm in range(-tj, tj + 1, 2)]
+    rng = np.random.default_rng(0)
+    for word in w[rng.integers(0, len(w), 200)]:
+        occ = [s for s in range(len(states)) if int(word) >> s & 1]
+        assert len(occ) == 12
+        assert sum(states[s][1] for s in occ) == 0
+        assert sum(SNSB_ORBITS[states[s][0]][1] for s in occ) % 2 == 0
 
 
 def test_dp_matches_enumeration_all_sectors():
