@@ -191,6 +191,8 @@ __global__ void dens_occ_kernel(GradArgs a, int64_t D) {
 void tbme_gradient(const Model& m, int n_eig, const double* w, const double* X, double* grad_v, double* grad_spe,
                    hipStream_t s) {
   TRBL_REQUIRE(m.has_h, TRBL_E_STATE, "no Hamiltonian set");
+  TRBL_REQUIRE(!m.fly, TRBL_E_INVALID,
+               "gradient needs the stored identical-particle operator (not built for wide single-species spaces)");
   TRBL_REQUIRE((int)m.orbits.size() <= 16, TRBL_E_INVALID, "gradient supports at most 16 orbits");
   const DeviceTables& d = m.dt;
   const int norb = (int)m.orbits.size();

@@ -160,6 +160,10 @@ void launch_apply(const Model& m, int precision, int nb, const void* V, int64_t 
   TRBL_REQUIRE(nb >= 1 && nb <= 64, TRBL_E_INVALID, "nb must be 1..64");
   TRBL_REQUIRE(ldv >= nb && ldw >= nb, TRBL_E_INVALID, "leading dimension smaller than nb");
   TRBL_REQUIRE(V && W && V != W, TRBL_E_INVALID, "V and W must be distinct device buffers");
+  if (m.fly) {
+    launch_fly(m, precision, nb, V, ldv, W, ldw, s);
+    return;
+  }
   if (precision == TRBL_FP64) run_hv<double>(m, nb, V, ldv, W, ldw, s);
   else run_hv<float>(m, nb, V, ldv, W, ldw, s);
   TRBL_HIP(hipGetLastError());

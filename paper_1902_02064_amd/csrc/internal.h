@@ -112,6 +112,9 @@ struct DeviceTables {
   DevBuf pp_term, nn_term;  // per CSR entry: list range into term lists
   DevBuf pp_tptr, pp_tid, pp_tsgn, nn_tptr, nn_tid, nn_tsgn;
   DevBuf h_term;            // per pn table entry: m-scheme pn term id (-1 if none)
+  // one species only, generated on the fly (fly.hip): ranking tables and the two-body terms
+  // grouped by creation pair
+  DevBuf fly_base, fly_rank, fly_perm, fly_soff, fly_sstart, fly_pstart, fly_cd, fly_h64, fly_h32, fly_e64, fly_e32;
 };
 
 // Work decomposition of one block H.V (hv.hip), owned by the model. The rows kernel is
@@ -163,11 +166,21 @@ struct Model {
   std::vector<int> h_off_host, h_ncol_host;
   std::vector<int> src_blk_host;        // per (block, class): source block or -1
   std::vector<int> sec_slice0[2];       // per species sector: first sliced-ELL slice
+  // one species empty and the other's sector too wide for the LDS-staged kernels: the
+  // identical-particle part is generated per element from the two-body terms (fly.hip)
+  bool fly = false;
+  int fly_s = 1;     // the occupied species
+  int fly_half = 0;  // m-states in the low part of the two-level ranking
 };
 
 // host helpers (model.cpp)
 void build_model(Model& m, const trbl_orbit* orbits, int n_orbits, int n_prot, int n_neut, int twoM, int parity);
 void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const trbl_tbme* v, int64_t n_v);
+// on-the-fly identical-particle H.V for single-species spaces (fly.hip)
+void build_fly_basis(Model& m);
+void build_fly_terms(Model& m);
+void launch_fly(const Model& m, int precision, int nb, const void* V, int64_t ldv, void* W, int64_t ldw,
+                hipStream_t s);
 double clebsch(int tj1, int tm1, int tj2, int tm2, int tJ, int tM);
 
 // device launchers (hv.hip)

@@ -3,6 +3,8 @@
 // kernels read: identical-particle operator rows and one-body jumps (App. B).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <functional>
 #include <map>
 #include <tuple>
 
@@ -55,7 +57,9 @@ static int below_sign(uint64_t w, int s) {
   return (popc(low) & 1) ? -1 : 1;
 }
 
-static void enumerate_species(const Model& m, Species& S, int npart) {
+// keep(2M, parity) selects the sectors that are stored (all when empty)
+static void enumerate_species(const Model& m, Species& S, int npart,
+                              const std::function<bool(int, int)>& keep = nullptr) {
   S.npart = npart;
   const int ns = m.ns;
   const int norb = (int)m.orbits.size();
@@ -81,6 +85,7 @@ static void enumerate_species(const Model& m, Species& S, int npart) {
     uint64_t part = 0;
     for (int o = 0; o < norb; o++) part = (part << 5) | (uint64_t)cnt[o];
     int par = (lsum & 1) ? -1 : 1;
+    if (keep && !keep(tm, par)) return;
     sec[{tm, -par}].push_back({part, rev, w});
   };
   if (npart == 0) {
@@ -149,8 +154,14 @@ void build_model(Model& m, const trbl_orbit* orbits, int n_orbits, int n_prot, i
   m.n_neut = n_neut;
   m.twoM = twoM;
   m.parity = parity;
-  enumerate_species(m, m.sp[0], n_prot);
-  enumerate_species(m, m.sp[1], n_neut);
+  // with one species empty only the sectors of the other that complete 2M and the parity are
+  // stored (the others belong to no block and are reached by no operator of the space)
+  auto keep_for = [&](int other) -> std::function<bool(int, int)> {
+    if (other != 0) return nullptr;
+    return [twoM, parity](int tm, int par) { return tm == twoM && (parity == 0 || par == parity); };
+  };
+  enumerate_species(m, m.sp[0], n_prot, keep_for(n_neut));
+  enumerate_species(m, m.sp[1], n_neut, keep_for(n_prot));
   // blocks: 2M_p ascending, proton parity + first, neutron parity + first
   struct Key {
     int tmp, pp, pn, kp, kn;
@@ -247,6 +258,17 @@ void build_model(Model& m, const trbl_orbit* orbits, int n_orbits, int n_prot, i
   m.dt.src_blk.upload(src);
   m.src_blk_host = src;
   m.has_h = false;
+  // single-species spaces too wide for the LDS-staged kernels (or any single-species space
+  // when TRBL_FLY=1, a switch for testing) generate the identical-particle part on the fly
+  m.fly = false;
+  if ((n_prot == 0) != (n_neut == 0)) {
+    m.fly_s = n_prot == 0 ? 1 : 0;
+    int widest = 0;
+    for (const auto& q : m.sp[m.fly_s].sectors) widest = std::max(widest, q.size);
+    const char* env = std::getenv("TRBL_FLY");
+    m.fly = widest > 2048 || (env && env[0] == '1');
+  }
+  if (m.fly) build_fly_basis(m);
 }
 
 // ------------------------------------------------------------------ interaction
@@ -359,6 +381,11 @@ void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const
   // Row g' of species s: <g'|H_ss|g> for every g reachable by a two-body jump, plus
   // the single-particle energies on the diagonal. Terms are grouped by creation pair
   // (a,b); the adjoint jump c+_c c+_d c_b c_a applied to g' gives g.
+  if (m.fly) {  // identical-particle part generated per element; no pn part in this space
+    build_fly_terms(m);
+    m.has_h = true;
+    return;
+  }
   for (int s = 0; s < 2; s++) {
     const Species& S = m.sp[s];
     const std::vector<MTerm>& T = s == 0 ? m.terms_pp : m.terms_nn;
@@ -537,7 +564,9 @@ void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const
           if (r0 & (1ull << y)) continue;
           int sy = sg * below_sign(r0, y);
           uint64_t r = r0 | (1ull << y);
-          int gi = S.index.at(r);
+          const auto found = S.index.find(r);
+          if (found == S.index.end()) continue;  // a sector not stored (the other species is empty)
+          int gi = found->second;
           int local = gi - S.sectors[S.sector_of[gi]].start;
           int c = ocls[x * ns + y];
           bucket[c].push_back({local, (oidx[x * ns + y] << 1) | (sy < 0 ? 1 : 0)});

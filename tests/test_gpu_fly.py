@@ -1,0 +1,118 @@
+"""Single-species spaces with the identical-particle part generated per element (GPU).
+
+Small spaces are forced onto that path (TRBL_FLY=1 at model creation) and compared with the
+oracle's explicit H; the 112Sn-shaped space (Sec. 4.2, D = 6,210,638) takes it by itself and
+is checked on sampled rows against the oracle, and through a short solve whose Ritz pairs
+are checked with the oracle's rows of H.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from gpu_common import fp32_bound, fp64_bound, pair, say
+from oracle.hamiltonian import Model as OracleModel
+from workloads import SD_ORBITS, SNSB_ORBITS, WORKLOADS, random_block, random_tbme
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+MIXED_PAR = ((0, 1, 1), (0, 2, 5), (0, 1, 3))
+
+CASES = [
+    # name, orbits, Z, N, 2M, parity, seed, nb
+    ("sd_n4", SD_ORBITS, 0, 4, 0, 0, 21, 4),
+    ("sd_z3_odd", SD_ORBITS, 3, 0, 1, 0, 22, 5),
+    ("mixpar_n3_both", MIXED_PAR, 0, 3, 1, 0, 23, 16),
+    ("mixpar_z2_neg", MIXED_PAR, 2, 0, 0, -1, 24, 1),
+    ("snsb_n4_pos", SNSB_ORBITS, 0, 4, 0, 1, 25, 20),
+]
+
+
+def _forced(orbits, z, n, twoM, tb, spe, par):
+    os.environ["TRBL_FLY"] = "1"
+    try:
+        return pair(orbits, z, n, twoM, tb, spe, spe, par)
+    finally:
+        del os.environ["TRBL_FLY"]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: c[0])
+def test_fly_matches_dense_oracle(case):
+    name, orbits, z, n, twoM, par, seed, nb = case
+    say("fly case", name)
+    spe = [(-0.8 + 0.5 * k) for k in range(len(orbits))]
+    tb = random_tbme(orbits, seed)
+    g, o = _forced(orbits, z, n, twoM, tb, spe, par)
+    assert g.dim == o.dim
+    H = o.dense()
+    nnz = int(np.max(np.count_nonzero(H, axis=1)))
+    V = random_block(200 + seed, o.dim, nb)
+    ref = H @ V
+    W = g.apply(torch.from_numpy(V).cuda()).cpu().numpy()
+    bound = fp64_bound(np.abs(H) @ np.abs(V), nnz)
+    say("fp64 max err / bound", np.max(np.abs(W - ref) / (bound + 1e-300)))
+    assert np.all(np.abs(W - ref) <= 4 * bound)
+    V32 = V.astype(np.float32)
+    W32 = g.apply(torch.from_numpy(V32).cuda()).cpu().numpy()
+    ref32 = H @ V32.astype(np.float64)
+    b32 = fp32_bound(np.abs(H) @ np.abs(V32.astype(np.float64)), nnz)
+    assert np.all(np.abs(W32 - ref32) <= 4 * b32)
+
+
+def test_fly_same_as_staged_path():
+    """The same small space through both paths: equal to rounding."""
+    tb = random_tbme(SNSB_ORBITS, 26)
+    spe = (0.0, 0.2, 1.5, 1.8, 2.4)
+    g1, _ = _forced(SNSB_ORBITS, 0, 3, 1, tb, spe, 0)
+    g0, _ = pair(SNSB_ORBITS, 0, 3, 1, tb, spe, spe, 0, oracle=False)
+    V = torch.from_numpy(random_block(31, g0.dim, 8)).cuda()
+    a, b = g0.apply(V).cpu().numpy(), g1.apply(V).cpu().numpy()
+    assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max()
+
+
+@pytest.fixture(scope="module")
+def sn112():
+    w = WORKLOADS["sn112"]
+    tb = w.tbme()
+    say("building sn112 (library, then oracle)")
+    g, _ = pair(w.orbits, w.n_prot, w.n_neut, w.twoM, tb, w.spe, w.spe, w.parity, oracle=False)
+    o = OracleModel(w.orbits, w.n_prot, w.n_neut, w.twoM, tb, w.spe, w.spe, w.parity)
+    return w, g, o
+
+
+def test_sn112_sampled_rows(sn112):
+    """112Sn shape (D = 6,210,638): sampled rows of H V (FP64, 16 columns) against the oracle's
+    rows of H, including both ends of the space."""
+    w, g, o = sn112
+    assert g.dim == o.dim == 6210638
+    V = random_block(41, g.dim, 16)
+    W = g.apply(torch.from_numpy(V).cuda()).cpu().numpy()
+    rows = np.unique(np.concatenate([[0, 1, g.dim - 2, g.dim - 1],
+                                     np.random.default_rng(5).integers(0, g.dim, 300)]))
+    ref = o.apply_rows(V, rows)
+    nnz = o.row_nnz(rows)
+    ptr, col, val = o.rows(rows)
+    absref = np.stack([np.abs(val[ptr[i]:ptr[i + 1]]) @ np.abs(V[col[ptr[i]:ptr[i + 1]]]) for i in range(len(rows))])
+    bound = fp64_bound(absref, int(nnz.max()))
+    err = np.abs(W[rows] - ref)
+    say("sn112 rows", len(rows), "max nnz", nnz.max(), "max err/bound", np.max(err / (bound + 1e-300)))
+    assert np.all(err <= 4 * bound)
+
+
+def test_sn112_solve_ritz_pairs(sn112):
+    """A short FP64 solve of the 112Sn shape; every returned Ritz pair is checked on sampled
+    rows with the oracle's H: |(H x)_i - theta x_i| small against |H| |x|."""
+    w, g, o = sn112
+    say("solve sn112")
+    ev, X, info = g.solve(w.nb, w.n_eig, w.l_s, w.l_m, w.tol, "fp64", vectors=True, check_every=-1)
+    say("sn112", info.iterations, "iterations, ev", ev[:4])
+    assert info.converged
+    assert np.all(np.diff(ev) >= -1e-9)
+    Xh = X.cpu().numpy()
+    rows = np.random.default_rng(6).integers(0, g.dim, 200)
+    HX = o.apply_rows(Xh, rows)
+    hn = np.abs(ev).max()
+    r = np.abs(HX - Xh[rows] * ev[None, :]).max()
+    say("sampled residual", r, "scale", hn)
+    assert r <= 1e-7 * hn

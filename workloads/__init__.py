@@ -177,6 +177,7 @@ class Workload:
 
 SD_SPE = (-3.9, -3.2, 2.1)
 PF_SPE = (0.0, 2.0, 4.0, 6.0)
+SNSB_SPE = (0.0, 0.2, 1.5, 1.8, 2.4)
 
 WORKLOADS = {
     # sd shell, 2+2 nucleons (20Ne shape, D = 640)
@@ -191,6 +192,10 @@ WORKLOADS = {
     # sd shell, 6+6 nucleons (28Si shape, D = 93,710): gradient workload
     "sd66": Workload("sd66", SD_ORBITS, 6, 6, 0, SD_SPE, nb=8, n_eig=20, l_s=40, l_m=120,
                      tol=1e-10, precision="fp64", extra={"grad_weight_seed": 7, "fd_step": 1e-5}),
+    # 50-82 neutron shell, 12 neutrons, positive parity (112Sn shape, D = 6,210,638): one
+    # species only, the identical-particle part generated per element
+    "sn112": Workload("sn112", SNSB_ORBITS, 0, 12, 0, SNSB_SPE, nb=8, n_eig=10, l_s=40, l_m=120,
+                      tol=1e-8, precision="fp64", parity=1),
     # pf shell, 6+6 nucleons (D = 109,954,620), mixed precision
     "pf66": Workload("pf66", PF_ORBITS, 6, 6, 0, PF_SPE, nb=32, n_eig=200, l_s=400, l_m=560,
                      tol=1e-5, precision="mixed"),
