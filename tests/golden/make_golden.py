@@ -1,6 +1,7 @@
 """Write the stored expected values of the full-size workloads, calling only the oracle.
 
   python tests/golden/make_golden.py [sd22] [sd66] [pf44]
+  python tests/golden/make_golden.py --nnz-only sn112
 
 Outputs (text, one value per line, header comments):
   <name>_nnz.txt     structural non-zero count of H (merged matrix elements)
@@ -32,7 +33,7 @@ def write(name, header, values, fmt="%.17g"):
             f.write((fmt % v) + "\n")
 
 
-def run(wname):
+def run(wname, nnz_only=False):
     w = WORKLOADS[wname]
     t0 = time.time()
     m = model_from_workload(w)
@@ -40,6 +41,8 @@ def run(wname):
     write(f"{wname}_nnz.txt", [f"{wname}: structural non-zeros of H (oracle rows, merged)", f"D = {m.dim}"],
           [nnz], "%d")
     print(wname, "D", m.dim, "nnz", nnz, flush=True)
+    if nnz_only:
+        return
     V1 = random_block(1000, m.dim, w.nb)
     tol = min(w.tol, 1e-10)
     hist = []
@@ -66,5 +69,8 @@ def run(wname):
 
 
 if __name__ == "__main__":
-    for name in (sys.argv[1:] or ["sd22", "sd66", "pf44"]):
-        run(name)
+    args = sys.argv[1:]
+    only = "--nnz-only" in args
+    names = [x for x in args if x != "--nnz-only"]
+    for name in (names or ["sd22", "sd66", "pf44"]):
+        run(name, only)
