@@ -239,7 +239,9 @@ def main():
         traffic = stored_traffic(a.workload)
         roof = {"bound": "alu", "achieved": flops / hv_launch / 1e12, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": flops / hv_launch / 1e12 / PEAK_FP64_TFLOPS, "traffic": traffic,
-                "kernel": "block H.V, FP64: hv_rows_kernel (one launch per sector-width bin) + hv_cols_kernel",
+                "kernel": ("block H.V, FP64: fly_kernel (single species, generated per element) + two row permutations"
+                           if (w.n_prot == 0) != (w.n_neut == 0) and D > 2048 else
+                           "block H.V, FP64: hv_rows_kernel (one launch per sector-width bin) + hv_cols_kernel"),
                 "measured_GBs": (traffic / hv_launch / 1e9) if traffic else None,
                 "per_launch": {"elements": nnz, "flops": flops, "compulsory_bytes": bytes_min,
                                "avg_duration_s": hv_launch}}

@@ -10,7 +10,11 @@
 //   internal(w) = base[sector][l] + rank[r]
 // numbers a sector densely (rank: position of r among the high patterns of its class in
 // increasing order; base: running sum over the low patterns of the size of their class).
-// perm maps the internal number to the Table-1 position inside the sector.
+// perm maps the internal number to the Table-1 position inside the sector. The product runs
+// in the internal order: V is gathered into it once, the kernel reads sources at their
+// internal numbers (determinants that differ only in the high part stay inside one low
+// pattern's contiguous range, which keeps many sources of neighbouring targets together),
+// and W is scattered back to Table-1 order.
 #include <map>
 #include <tuple>
 
@@ -39,6 +43,7 @@ void build_fly_basis(Model& m) {
   for (uint64_t r = 0; r < (1ull << high); r++) rank[r] = count[key_of(r, half)]++;
   const int nsec = (int)S.sectors.size();
   std::vector<int> base((size_t)nsec << half), perm(S.words.size()), sstart(nsec);
+  std::vector<uint64_t> wint(S.words.size());
   std::vector<int64_t> soff(nsec + 1, -1);
   for (int k = 0; k < nsec; k++) {
     const SpeciesSector& q = S.sectors[k];
@@ -54,7 +59,9 @@ void build_fly_basis(Model& m) {
     TRBL_REQUIRE(run == q.size, TRBL_E_INVALID, "two-level ranking does not reproduce the sector");
     for (int i = 0; i < q.size; i++) {
       const uint64_t w = S.words[q.start + i];
-      perm[q.start + base[((size_t)k << half) | (w & ((1ull << half) - 1))] + rank[w >> half]] = i;
+      const int in = base[((size_t)k << half) | (w & ((1ull << half) - 1))] + rank[w >> half];
+      perm[q.start + in] = i;
+      wint[q.start + in] = w;
     }
     sstart[k] = q.start;
     for (const auto& b : m.blocks)
@@ -65,6 +72,7 @@ void build_fly_basis(Model& m) {
   m.dt.fly_base.upload(base);
   m.dt.fly_rank.upload(rank);
   m.dt.fly_perm.upload(perm);
+  m.dt.fly_wint.upload(wint);
   m.dt.fly_soff.upload(soff);
   m.dt.fly_sstart.upload(sstart);
 }
@@ -104,12 +112,10 @@ struct FlyArgs {
   T* W;
   int64_t ldv, ldw, D;
   int nb, ns, half, nsec;
-  const int64_t* soff;  // first M-scheme index of each sector (nsec + 1)
-  const int* sstart;    // first species index of each sector
-  const uint64_t* words;
+  const int* sstart;     // first species index of each sector (internal numbering starts there too)
+  const uint64_t* words;  // determinants in the internal order
   const int* base;
   const int* rank;
-  const int* perm;
   const int* pstart;
   const int2* cd;
   const T* h;
@@ -118,26 +124,26 @@ struct FlyArgs {
 
 __device__ __forceinline__ int jw_odd(uint64_t w, int s) { return __popcll(w & ((1ull << s) - 1)) & 1; }
 
-// One thread per target determinant w and C columns: W[w] = (sum of the single-particle energies of
-// w) V[w] + sum over occupied pairs a < b and terms (c, d) of that creation pair of
-// sign * h * V[source], source = w with a, b removed and d, c added (the adjoint of the term
-// c+_a c+_b c_d c_c applied to w), the sign counting the occupied states below each operator.
+// One thread per target determinant w (internal order) and C columns: W[w] = (sum of the
+// single-particle energies of w) V[w] + sum over occupied pairs a < b and terms (c, d) of that
+// creation pair of sign * h * V[source], source = w with a, b removed and d, c added (the
+// adjoint of the term c+_a c+_b c_d c_c applied to w), the sign counting the occupied states
+// below each operator. V and W are in the internal order, nb columns apart.
 template <class T, int C>
 __global__ __launch_bounds__(256) void fly_kernel(FlyArgs<T> a) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= a.D) return;
   const int c0 = blockIdx.y * C, cv = min(C, a.nb - c0);
   int k = 0;
-  while (k + 1 < a.nsec && t >= a.soff[k + 1]) k++;
-  const int64_t so = a.soff[k];
-  const int* pk = a.perm + a.sstart[k];
+  while (k + 1 < a.nsec && t >= a.sstart[k + 1]) k++;
+  const int64_t st = a.sstart[k];
   const int* bk = a.base + ((int64_t)k << a.half);
-  const uint64_t w = a.words[a.sstart[k] + (t - so)];
+  const uint64_t w = a.words[t];
   const uint64_t lmask = (1ull << a.half) - 1;
   T acc[C];
   T e = T(0);
   for (uint64_t x = w; x; x &= x - 1) e += a.e[__builtin_ctzll(x)];
-  const T* vt = a.V + t * a.ldv + c0;
+  const T* vt = a.V + t * a.nb + c0;
 #pragma unroll
   for (int c = 0; c < C; c++) acc[c] = c < cv ? e * vt[c] : T(0);
   for (uint64_t x = w; x; x &= x - 1) {
@@ -160,41 +166,64 @@ __global__ __launch_bounds__(256) void fly_kernel(FlyArgs<T> a) {
         if ((r >> p.x) & 1) continue;
         s2 ^= jw_odd(r, p.x);
         r |= 1ull << p.x;
-        const int64_t j = so + pk[bk[r & lmask] + a.rank[r >> a.half]];
+        const int64_t j = st + bk[r & lmask] + a.rank[r >> a.half];
         const T hv = s2 ? -a.h[q] : a.h[q];
-        const T* vs = a.V + j * a.ldv + c0;
+        const T* vs = a.V + j * a.nb + c0;
 #pragma unroll
         for (int c = 0; c < C; c++)
           if (c < cv) acc[c] += hv * vs[c];
       }
     }
   }
-  T* wt = a.W + t * a.ldw + c0;
+  T* wt = a.W + t * a.nb + c0;
 #pragma unroll
   for (int c = 0; c < C; c++)
     if (c < cv) wt[c] = acc[c];
 }
 
+// rows between the Table-1 order (leading dimension ld) and the internal order (packed, nb):
+// internal row i of sector k is Table-1 row soff[k] + perm[i]
+template <class T>
+__global__ void fly_permute_kernel(const T* src, int64_t lds_, T* dst, int64_t ldd, int nb, int64_t n, int nsec,
+                                   const int* sstart, const int64_t* soff, const int* perm, int to_internal) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n * nb) return;
+  const int64_t i = e / nb;
+  const int c = (int)(e - i * nb);
+  int k = 0;
+  while (k + 1 < nsec && i >= sstart[k + 1]) k++;
+  const int64_t row = soff[k] + perm[i];
+  if (to_internal) dst[i * ldd + c] = src[row * lds_ + c];
+  else dst[row * ldd + c] = src[i * lds_ + c];
+}
+
 template <class T>
 static void run_fly(const Model& m, int nb, const void* V, int64_t ldv, void* W, int64_t ldw, hipStream_t s) {
-  constexpr int C = 16;
   FlyArgs<T> a{};
-  a.V = static_cast<const T*>(V);
-  a.W = static_cast<T*>(W);
-  a.ldv = ldv;
-  a.ldw = ldw;
-  a.D = m.dim;
+  const int64_t D = m.dim;
+  const DeviceTables& d = m.dt;
+  // internal-order copies of V and W, kept with the model for the next product
+  DevBuf& buf = m.fly_buf[sizeof(T) == 8 ? 1 : 0];
+  buf.alloc((size_t)2 * D * nb * sizeof(T));
+  T* vin = buf.as<T>();
+  T* win = vin + D * nb;
+  const int nsec = (int)m.sp[m.fly_s].sectors.size();
+  const int64_t ne = D * nb;
+  const unsigned g1 = (unsigned)((ne + 255) / 256);
+  hipLaunchKernelGGL((fly_permute_kernel<T>), dim3(g1), dim3(256), 0, s, static_cast<const T*>(V), ldv, vin,
+                     (int64_t)nb, nb, D, nsec, d.fly_sstart.as<int>(), d.fly_soff.as<int64_t>(),
+                     d.fly_perm.as<int>(), 1);
+  a.V = vin;
+  a.W = win;
+  a.D = D;
   a.nb = nb;
   a.ns = m.ns;
   a.half = m.fly_half;
-  a.nsec = (int)m.sp[m.fly_s].sectors.size();
-  const DeviceTables& d = m.dt;
-  a.soff = d.fly_soff.as<int64_t>();
+  a.nsec = nsec;
   a.sstart = d.fly_sstart.as<int>();
-  a.words = (m.fly_s == 1 ? d.nwords : d.pwords).as<uint64_t>();
+  a.words = d.fly_wint.as<uint64_t>();
   a.base = d.fly_base.as<int>();
   a.rank = d.fly_rank.as<int>();
-  a.perm = d.fly_perm.as<int>();
   a.pstart = d.fly_pstart.as<int>();
   a.cd = d.fly_cd.as<int2>();
   if constexpr (sizeof(T) == 8) {
@@ -204,8 +233,15 @@ static void run_fly(const Model& m, int nb, const void* V, int64_t ldv, void* W,
     a.h = d.fly_h32.as<T>();
     a.e = d.fly_e32.as<T>();
   }
-  const dim3 grid((unsigned)((m.dim + 255) / 256), (unsigned)((nb + C - 1) / C));
-  hipLaunchKernelGGL((fly_kernel<T, C>), grid, dim3(256), 0, s, a);
+  if (nb <= 8) {
+    const dim3 grid((unsigned)((D + 255) / 256), 1);
+    hipLaunchKernelGGL((fly_kernel<T, 8>), grid, dim3(256), 0, s, a);
+  } else {
+    const dim3 grid((unsigned)((D + 255) / 256), (unsigned)((nb + 15) / 16));
+    hipLaunchKernelGGL((fly_kernel<T, 16>), grid, dim3(256), 0, s, a);
+  }
+  hipLaunchKernelGGL((fly_permute_kernel<T>), dim3(g1), dim3(256), 0, s, win, (int64_t)nb, static_cast<T*>(W), ldw,
+                     nb, D, nsec, d.fly_sstart.as<int>(), d.fly_soff.as<int64_t>(), d.fly_perm.as<int>(), 0);
 }
 
 void launch_fly(const Model& m, int precision, int nb, const void* V, int64_t ldv, void* W, int64_t ldw,

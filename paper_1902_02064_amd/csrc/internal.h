@@ -114,7 +114,8 @@ struct DeviceTables {
   DevBuf h_term;            // per pn table entry: m-scheme pn term id (-1 if none)
   // one species only, generated on the fly (fly.hip): ranking tables and the two-body terms
   // grouped by creation pair
-  DevBuf fly_base, fly_rank, fly_perm, fly_soff, fly_sstart, fly_pstart, fly_cd, fly_h64, fly_h32, fly_e64, fly_e32;
+  DevBuf fly_base, fly_rank, fly_perm, fly_wint, fly_soff, fly_sstart, fly_pstart, fly_cd, fly_h64, fly_h32, fly_e64,
+      fly_e32;
 };
 
 // Work decomposition of one block H.V (hv.hip), owned by the model. The rows kernel is
@@ -171,6 +172,7 @@ struct Model {
   bool fly = false;
   int fly_s = 1;     // the occupied species
   int fly_half = 0;  // m-states in the low part of the two-level ranking
+  mutable DevBuf fly_buf[2];  // V and W in the internal order (FP32, FP64)
 };
 
 // host helpers (model.cpp)
