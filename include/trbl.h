@@ -92,6 +92,11 @@ typedef struct {
   int criterion;   /* TRBL_CONV_RESIDUAL (0): rho_i <= tol * max|theta|;
                       TRBL_CONV_RITZ_CHANGE (1): the paper's test of Sec. 4.1, the n_eig lowest Ritz
                       values move by at most tol (absolute) between two consecutive tests */
+  const double* mask; /* optional device [D] of 0/1 (e.g. from trbl_occupation_mask); NULL = none.
+                      When set the solve works in the subspace of the basis states with mask 1:
+                      H is replaced by P H P (P = diag(mask)), the start block and every
+                      replacement vector are projected, so eigenpairs of the truncated space
+                      come out (start vectors of Sec. 4.2). Must stay valid during the call. */
 } trbl_opts;
 
 typedef struct {
@@ -153,6 +158,13 @@ int trbl_tbme_grad(const trbl_model* m, const trbl_opts* opts, int n_eig, const 
    in the single-particle energies, two-body part J(J+1) - ja(ja+1) - jb(jb+1) on diagonal pair
    elements) this gives <J^2> of Ritz vectors. Allocates one [D][min(n,64)] FP64 block. */
 int trbl_expect(const trbl_model* m, int n, const void* X, double* out, void* stream);
+
+/* Particle-hole truncation of Sec. 4.2 (e.g. at most 4 nucleons above the N = 64 subshell gap):
+   mask[i] = 1.0 if basis state i has at most max_particles nucleons (protons plus neutrons) in
+   the orbits orbit_set[0 .. n_set-1] (host array of orbit indices), else 0.0. mask: device [D]
+   FP64, written on `stream`. Errors: TRBL_E_INVALID for a bad orbit index or a negative bound. */
+int trbl_occupation_mask(const trbl_model* m, const int* orbit_set, int n_set, int max_particles, double* mask,
+                         void* stream);
 
 /* Message of the last failing call on this thread. */
 const char* trbl_last_error(void);

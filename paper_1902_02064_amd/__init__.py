@@ -40,7 +40,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("nb", ctypes.c_int), ("n_eig", ctypes.c_int), ("l_s", ctypes.c_int), ("l_m", ctypes.c_int),
                 ("max_iter", ctypes.c_int), ("tol", ctypes.c_double), ("precision", ctypes.c_int),
                 ("refine", ctypes.c_int), ("seed", ctypes.c_uint64), ("v0", ctypes.c_void_p),
-                ("stream", ctypes.c_void_p), ("check_every", ctypes.c_int), ("criterion", ctypes.c_int)]
+                ("stream", ctypes.c_void_p), ("check_every", ctypes.c_int), ("criterion", ctypes.c_int),
+                ("mask", ctypes.c_void_p)]
 
 
 class Info(ctypes.Structure):
@@ -78,6 +79,7 @@ def load():
         "trbl_solve": ([P, ctypes.POINTER(Opts), P, P, ctypes.POINTER(Info)], I),
         "trbl_tbme_grad": ([P, ctypes.POINTER(Opts), I, P, P, P, P], I),
         "trbl_expect": ([P, I, P, P, P], I),
+        "trbl_occupation_mask": ([P, P, I, I, P, P], I),
         "trbl_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -93,6 +95,11 @@ def header_symbols():
     import re
     text = open(HEADER).read()
     return sorted(set(re.findall(r"\b(trbl_[a-z_]+)\s*\(", text)))
+
+
+def torch_float64():
+    import torch
+    return torch.float64
 
 
 def _check(rc):
@@ -173,6 +180,15 @@ class Model:
         _check(load().trbl_basis_unrank_dev(self._h, _ptr(idx), idx.numel(), _ptr(p), _ptr(n), _stream()))
         return p, n
 
+    def occupation_mask(self, orbit_set, max_particles):
+        """Device [D] FP64 mask of the basis states with at most max_particles nucleons in the
+        given orbits (the particle-hole truncation of Sec. 4.2)."""
+        import torch
+        orb = (ctypes.c_int * max(1, len(orbit_set)))(*orbit_set)
+        mask = torch.empty(self.dim, dtype=torch.float64, device="cuda")
+        _check(load().trbl_occupation_mask(self._h, orb, len(orbit_set), max_particles, _ptr(mask), _stream()))
+        return mask
+
     def rank_dev(self, pbits, nbits):
         import torch
         pbits = pbits.to(torch.int64).contiguous()
@@ -216,7 +232,7 @@ class Model:
 
     # -- eigensolver
     def _opts(self, nb, n_eig, l_s, l_m, tol, precision, max_iter, seed, v0, refine, check_every=1,
-              criterion="residual"):
+              criterion="residual", mask=None):
         o = Opts()
         o.nb, o.n_eig, o.l_s, o.l_m, o.max_iter = nb, n_eig, l_s, l_m, max_iter
         o.tol = tol
@@ -227,13 +243,18 @@ class Model:
         o.stream = _stream().value
         o.check_every = check_every
         o.criterion = {"residual": 0, "ritz_change": 1}[criterion]
+        if mask is not None:
+            assert mask.is_cuda and mask.dtype == torch_float64() and mask.numel() == self.dim and mask.is_contiguous()
+        o.mask = None if mask is None else mask.data_ptr()
         return o
 
     def solve(self, nb, n_eig, l_s, l_m, tol, precision="fp64", max_iter=5000, seed=1000, v0=None,
-              refine=True, vectors=False, check_every=1, criterion="residual"):
-        """Lowest eigenpairs by TRBL (Alg. 4). Returns (evals, evecs or None, SolveInfo)."""
+              refine=True, vectors=False, check_every=1, criterion="residual", mask=None):
+        """Lowest eigenpairs by TRBL (Alg. 4). Returns (evals, evecs or None, SolveInfo).
+        mask: optional device [D] 0/1 FP64 (occupation_mask): solve in that truncated subspace."""
         import torch
-        o = self._opts(nb, n_eig, l_s, l_m, tol, precision, max_iter, seed, v0, refine, check_every, criterion)
+        o = self._opts(nb, n_eig, l_s, l_m, tol, precision, max_iter, seed, v0, refine, check_every, criterion,
+                       mask)
         ev = (ctypes.c_double * n_eig)()
         res = (ctypes.c_double * n_eig)()
         info = Info()

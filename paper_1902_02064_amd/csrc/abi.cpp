@@ -109,6 +109,16 @@ int trbl_basis_unrank_dev(const trbl_model* h, const int64_t* idx, int64_t n, ui
   });
 }
 
+int trbl_occupation_mask(const trbl_model* h, const int* orbit_set, int n_set, int max_particles, double* mask,
+                         void* stream) {
+  return guarded([&] {
+    TRBL_REQUIRE(h && mask && n_set >= 0 && (n_set == 0 || orbit_set) && max_particles >= 0, TRBL_E_INVALID,
+                 "bad argument");
+    trbl::launch_occupation_mask(h->m, orbit_set, n_set, max_particles, mask, (hipStream_t)stream);
+    return TRBL_OK;
+  });
+}
+
 int trbl_basis_rank_dev(const trbl_model* h, const uint64_t* pbits, const uint64_t* nbits, int64_t n, int64_t* idx,
                         void* stream) {
   return guarded([&] {

@@ -40,6 +40,9 @@ template <class T>
 void random_block(T* out, int64_t ld, int64_t D, int nb, uint64_t seed, hipStream_t st);
 template <class TS, class TD>
 void copy_cols(const TS* src, int64_t lds_, TD* dst, int64_t ldd, int64_t D, int ncol, hipStream_t st);
+// X[r, 0:ncol] = 0 where mask[r] == 0 (no-op for a null mask)
+template <class T>
+void mask_rows(T* X, int64_t ld, int64_t D, int ncol, const double* mask, hipStream_t st);
 void t_alpha(double* T, int ldt, int c0, int nb, const double* C1, hipStream_t st);
 // C[r, :] = T[r, c0:c0+nb] for r in [r_lo, c0) (C row-major, nb columns)
 void t_column(const double* T, int ldt, int c0, int r_lo, int nb, double* C, hipStream_t st);

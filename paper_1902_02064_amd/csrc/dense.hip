@@ -672,6 +672,14 @@ __global__ void random_kernel(T* out, int64_t ld, int64_t D, int nb, uint64_t se
   out[(e / nb) * ld + e % nb] = (T)z;
 }
 
+template <class T>
+__global__ void mask_rows_kernel(T* X, int64_t ld, int64_t D, int ncol, const double* __restrict__ mask) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= D * ncol) return;
+  const int64_t r = e / ncol;
+  if (mask[r] == 0.0) X[r * ld + (e - r * ncol)] = T(0);
+}
+
 template <class TS, class TD>
 __global__ void copy_cols_kernel(const TS* src, int64_t lds_, TD* dst, int64_t ldd, int64_t D, int ncol) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -895,6 +903,14 @@ void random_block(T* out, int64_t ld, int64_t D, int nb, uint64_t seed, hipStrea
   TRBL_HIP(hipGetLastError());
 }
 
+template <class T>
+void mask_rows(T* X, int64_t ld, int64_t D, int ncol, const double* mask, hipStream_t st) {
+  if (!mask) return;
+  const int64_t n = D * ncol;
+  hipLaunchKernelGGL(mask_rows_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, X, ld, D, ncol, mask);
+  TRBL_HIP(hipGetLastError());
+}
+
 template <class TS, class TD>
 void copy_cols(const TS* src, int64_t lds_, TD* dst, int64_t ldd, int64_t D, int ncol, hipStream_t st) {
   const int64_t n = D * ncol;
@@ -955,6 +971,8 @@ template void rowgemm<float, double>(const float*, int64_t, int, const double*, 
                                      int64_t, int, int, int, hipStream_t);
 template void random_block<double>(double*, int64_t, int64_t, int, uint64_t, hipStream_t);
 template void random_block<float>(float*, int64_t, int64_t, int, uint64_t, hipStream_t);
+template void mask_rows<double>(double*, int64_t, int64_t, int, const double*, hipStream_t);
+template void mask_rows<float>(float*, int64_t, int64_t, int, const double*, hipStream_t);
 template void copy_cols<double, double>(const double*, int64_t, double*, int64_t, int64_t, int, hipStream_t);
 template void copy_cols<float, float>(const float*, int64_t, float*, int64_t, int64_t, int, hipStream_t);
 template void copy_cols<float, double>(const float*, int64_t, double*, int64_t, int64_t, int, hipStream_t);

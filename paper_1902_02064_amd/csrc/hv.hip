@@ -267,6 +267,23 @@ __global__ void unrank_kernel(RankArgs a, const int64_t* idx, int64_t n, uint64_
   nbits[i] = a.words[1][a.blk_n0[lo] + rel % dn];
 }
 
+// mask[i] = 1 when basis state i has at most maxp nucleons in the states of `set`
+__global__ void occupation_mask_kernel(RankArgs a, uint64_t set, int maxp, int64_t D, double* mask) {
+  const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (x >= D) return;
+  int lo = 0, hi = a.nblocks - 1;
+  while (lo < hi) {  // last block with offset <= x
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.blk_off[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  const int64_t rel = x - a.blk_off[lo];
+  const int dn = a.blk_dn[lo];
+  const uint64_t pw = a.words[0][a.blk_p0[lo] + rel / dn];
+  const uint64_t nw = a.words[1][a.blk_n0[lo] + rel % dn];
+  mask[x] = (__popcll(pw & set) + __popcll(nw & set) <= maxp) ? 1.0 : 0.0;
+}
+
 static RankArgs rank_args(const Model& m) {
   RankArgs a{};
   a.ns = m.ns;
@@ -300,6 +317,19 @@ void launch_rank(const Model& m, const uint64_t* pb, const uint64_t* nbits, int6
   RankArgs a = rank_args(m);
   const int64_t nbk = (n + 255) / 256;
   hipLaunchKernelGGL(rank_kernel, dim3((unsigned)nbk), dim3(256), 0, s, a, pb, nbits, n, idx);
+  TRBL_HIP(hipGetLastError());
+}
+
+void launch_occupation_mask(const Model& m, const int* orbit_set, int n_set, int maxp, double* mask, hipStream_t s) {
+  uint64_t set = 0;
+  for (int k = 0; k < n_set; k++) {
+    TRBL_REQUIRE(orbit_set[k] >= 0 && orbit_set[k] < (int)m.orbits.size(), TRBL_E_INVALID, "orbit index out of range");
+    for (int st = 0; st < m.ns; st++)
+      if (m.st_orb[st] == orbit_set[k]) set |= 1ull << st;
+  }
+  RankArgs a = rank_args(m);
+  const int64_t nbk = (m.dim + 255) / 256;
+  hipLaunchKernelGGL(occupation_mask_kernel, dim3((unsigned)nbk), dim3(256), 0, s, a, set, maxp, m.dim, mask);
   TRBL_HIP(hipGetLastError());
 }
 

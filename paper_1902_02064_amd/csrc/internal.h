@@ -190,6 +190,7 @@ void launch_apply(const Model& m, int precision, int nb, const void* V, int64_t 
                   hipStream_t s);
 void launch_rank(const Model& m, const uint64_t* pb, const uint64_t* nb, int64_t n, int64_t* idx, hipStream_t s);
 void launch_unrank(const Model& m, const int64_t* idx, int64_t n, uint64_t* pb, uint64_t* nb, hipStream_t s);
+void launch_occupation_mask(const Model& m, const int* orbit_set, int n_set, int maxp, double* mask, hipStream_t s);
 
 // solver (solver.cpp)
 int solve(const Model& m, const trbl_opts& o, double* evals, void* evecs, trbl_info* info);

@@ -149,6 +149,7 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
       double nr = dot_xx();
       if (!(nr > 1e-10 * wmax) || !(wmax > 0.0)) {
         random_block<double>(x, 1, D, 1, o.seed ^ (0x9E3779B97F4A7C15ull * (salt + 1 + j)), st);
+        mask_rows<double>(x, 1, D, 1, o.mask, st);
         orth_against(mprev + j, nullptr);
         nr = dot_xx();
         TRBL_REQUIRE(nr > 0.0, TRBL_E_BREAKDOWN, "no vector left outside the Krylov basis");
@@ -170,6 +171,7 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
     copy_cols<TQ, TQ>(static_cast<const TQ*>(o.v0), nb, Q, ldq, D, nb, st);
   else
     random_block<TQ>(Q, ldq, D, nb, o.seed, st);
+  mask_rows<TQ>(Q, ldq, D, nb, o.mask, st);
   tn<TQ, TQ>(Q, ldq, nb, Q, ldq, nb, D, C1, sc, st);
   chol(C1, 1, nb, R1, R1i, nullptr, nullptr, status, st);
   apply_small<TQ, double>(Q, ldq, R1i, W, nb, nb, D, true, sc, st);
@@ -185,6 +187,7 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
       random_block<TQ>(Q, ldq, D, nb, o.seed, st);
       copy_cols<TQ, double>(Q, ldq, W, nb, D, nb, st);
     }
+    mask_rows<double>(W, nb, D, nb, o.mask, st);
     robust_qr(W, 0, 0);
   }
 
@@ -206,6 +209,8 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
     // W := H V_k
     void* Wh = mixed ? (void*)W32 : (void*)W;
     launch_apply(m, mixed ? TRBL_MIXED : TRBL_FP64, nb, Vk, nb, Wh, nb, st);
+    if (mixed) mask_rows<float>(W32, nb, D, nb, o.mask, st);
+    else mask_rows<double>(W, nb, D, nb, o.mask, st);
     TRBL_HIP(hipEventRecord(ev.e[1], st));
     // alpha_k = V_k^T W, then block classical Gram-Schmidt twice against all stored vectors.
     // The first pass takes its coefficients from T: in exact arithmetic Q^T H V_k is the
@@ -243,6 +248,8 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
       // breakdown: W was scaled in place; form it again (same arithmetic) and take the
       // column-wise QR with replacement
       launch_apply(m, mixed ? TRBL_MIXED : TRBL_FP64, nb, Vk, nb, Wh, nb, st);
+      if (mixed) mask_rows<float>(W32, nb, D, nb, o.mask, st);
+      else mask_rows<double>(W, nb, D, nb, o.mask, st);
       if (mixed) {
         tn<float, float>((const float*)Q, ldq, mcur, W32, nb, nb, D, C1, sc, st);
         update<float, float>((const float*)Q, ldq, mcur, C1, W32, nb, W, nb, nb, D, 1, C2, sc, st);
@@ -369,6 +376,7 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
       const int w = std::min(cw, neig - c);
       copy_cols<TQ, double>(Q + c, ldq, Xc.as<double>(), w, D, w, st);
       launch_apply(m, TRBL_FP64, w, Xc.as<double>(), w, Hc.as<double>(), w, st);
+      mask_rows<double>(Hc.as<double>(), w, D, w, o.mask, st);
       tn<TQ, double>(Q, ldq, neig, Hc.as<double>(), w, w, D, tmp.as<double>(), sc, st);
       copy_cols<double, double>(tmp.as<double>(), w, S + c, neig, neig, w, st);
       tn<TQ, double>(Q, ldq, neig, Xc.as<double>(), w, w, D, tmp.as<double>(), sc, st);
@@ -389,6 +397,7 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
       for (int c = 0; c < neig; c += cw) {
         const int w = std::min(std::min(cw, 64), neig - c);
         launch_apply(m, TRBL_FP64, w, X + c, neig, Hc.as<double>(), w, st);
+        mask_rows<double>(Hc.as<double>(), w, D, w, o.mask, st);
         resid_cols(Hc.as<double>(), w, X + c, neig, th2.as<double>() + c, w, D, rs.as<double>() + c, sc, st);
       }
       TRBL_HIP(hipMemcpyAsync(res.data(), rs.as<double>(), neig * sizeof(double), hipMemcpyDeviceToHost, st));
