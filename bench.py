@@ -42,6 +42,16 @@ def parse():
     p.add_argument("--calib-copy", action="store_true",
                    help="with --hv-only: also run a plain 1 GiB device copy (counter calibration)")
     p.add_argument("--check-every", type=int, default=-1, help="convergence-test period; -1 = adaptive")
+    p.add_argument("--truncated-start", action="store_true",
+                   help="start vectors from a truncated subspace (Sec. 4.2) instead of the benchmark: nb vectors "
+                        "of the space with at most --trunc-max nucleons in --trunc-orbits start the full solve, "
+                        "against a random start of the same block size")
+    p.add_argument("--trunc-orbits", default="2,3,4", help="orbit indices of the truncation (sn112: above N = 64)")
+    p.add_argument("--trunc-max", type=int, default=4)
+    p.add_argument("--trunc-nb", type=int, default=16)
+    p.add_argument("--trunc-spe", default="",
+                   help="comma-separated single-particle energies for the truncated-start run (default: the "
+                        "workload's); e.g. a wide gap above the truncation orbits")
     p.add_argument("--sweep", action="store_true",
                    help="block-size sweep instead of the benchmark: H.V time and TRBL solve for the 32 lowest, "
                         "nb = 1..32, l_s = 40, l_m = max(200, 40 + 10 nb)")
@@ -157,6 +167,46 @@ def sweep(model, w, torch, np):
                       "workload": w.name, "n_eig": 32, "l_s": 40, "l_m": "max(200, 40 + 10 nb)", "tol": 1e-8}))
 
 
+def truncated_start(model, w, a, torch):
+    """Sec. 4.2: nb start vectors from the truncated space (at most trunc_max nucleons in the
+    given orbits) against a random start block, for the workload's lowest n_eig."""
+    nb = a.trunc_nb
+    orbs = [int(x) for x in a.trunc_orbits.split(",") if x != ""]
+    spe = list(w.spe)
+    if a.trunc_spe:
+        spe = [float(x) for x in a.trunc_spe.split(",")]
+        model.set_hamiltonian(spe, spe, w.tbme())
+    ls, lm = 4 * nb, 16 * nb
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mask = model.occupation_mask(orbs, a.trunc_max)
+    kept = int(mask.sum().item())
+    print(f"# truncated space: {kept} of {model.dim} states; solving for {nb} vectors", file=sys.stderr, flush=True)
+    et, Xt, it_t = model.solve(nb, nb, ls, lm, 1e-4, "fp64", max_iter=2000, vectors=True, mask=mask, check_every=-1)
+    print(f"# truncated solve: {it_t.iterations} iterations, converged {it_t.converged}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_trunc = time.perf_counter() - t0
+    del mask
+    runs = {}
+    for name, v0 in (("truncated_start", Xt.contiguous()), ("random_start", None)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        print(f"# full solve, {name}", file=sys.stderr, flush=True)
+        ev, _, info = model.solve(nb, w.n_eig, ls, lm, w.tol, "fp64", max_iter=2000, v0=v0, check_every=-1)
+        torch.cuda.synchronize()
+        runs[name] = {"s": time.perf_counter() - t0, "iterations": info.iterations, "restarts": info.restarts,
+                      "converged": info.converged, "e0": float(ev[0]), "e_last": float(ev[-1])}
+        print("# " + name + " " + json.dumps(runs[name]), file=sys.stderr, flush=True)
+    print(json.dumps({"truncated_start": {
+        "workload": w.name, "D": model.dim, "spe": spe,
+        "truncation": {"orbits": orbs, "max_nucleons": a.trunc_max, "kept": kept},
+        "nb": nb, "n_eig": w.n_eig, "l_s": ls, "l_m": lm, "tol": w.tol,
+        "truncated_solve": {"s": t_trunc, "iterations": it_t.iterations, "converged": it_t.converged, "tol": 1e-4,
+                            "e0": float(et[0]), "e_last": float(et[-1])},
+        "full": runs,
+        "speedup_incl_truncated": runs["random_start"]["s"] / (runs["truncated_start"]["s"] + t_trunc)}}))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -193,6 +243,9 @@ def main():
 
     if a.sweep:
         sweep(model, w, torch, np)
+        return
+    if a.truncated_start:
+        truncated_start(model, w, a, torch)
         return
 
     def solve(prec):
