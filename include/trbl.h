@@ -106,7 +106,12 @@ typedef struct {
 } trbl_info;
 
 /* Build the M-scheme product basis (Sec. 2, App. A). parity: +1, -1, or 0 for both.
-   Copies the orbit list. *out owns host and device tables until trbl_model_destroy. */
+   Copies the orbit list. *out owns host and device tables until trbl_model_destroy.
+   With one species empty (single-species spaces of Sec. 4.2) only the sectors of the other
+   species that form the space are enumerated; when the widest of them exceeds 2048
+   determinants (or the environment variable TRBL_FLY is "1" at this call) the products
+   generate the identical-particle part per element instead of storing it, which needs at most
+   44 m-states and keeps two [D][nb] work blocks per precision with the model. */
 int trbl_model_create(const trbl_orbit* orbits, int n_orbits, int n_prot, int n_neut, int twoM,
                       int parity, trbl_model** out);
 void trbl_model_destroy(trbl_model* m);
@@ -148,7 +153,8 @@ int trbl_solve(const trbl_model* m, const trbl_opts* opts, double* evals, void* 
 /* Gradient of sum_k w_k E_k (Hellmann-Feynman) with respect to every element of the last
    trbl_set_hamiltonian list (grad_v, host n_v) and optionally the proton then neutron
    single-particle energies (grad_spe, host 2*n_orbits, may be NULL).
-   evecs: device [D][n_eig] FP64 eigenvectors; NULL = recompute them with trbl_solve(opts). */
+   evecs: device [D][n_eig] FP64 eigenvectors; NULL = recompute them with trbl_solve(opts).
+   TRBL_E_INVALID for single-species spaces that generate their operator per element. */
 int trbl_tbme_grad(const trbl_model* m, const trbl_opts* opts, int n_eig, const double* w,
                    const void* evecs, double* grad_v, double* grad_spe);
 
