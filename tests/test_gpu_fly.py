@@ -12,7 +12,7 @@ import pytest
 
 from gpu_common import fp32_bound, fp64_bound, pair, say
 from oracle.hamiltonian import Model as OracleModel
-from workloads import SD_ORBITS, SNSB_ORBITS, WORKLOADS, random_block, random_tbme
+from workloads import SD_ORBITS, SNSB_ORBITS, WORKLOADS, jsquared_spe, jsquared_tbme, random_block, random_tbme
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -116,3 +116,11 @@ def test_sn112_solve_ritz_pairs(sn112):
     r = np.abs(HX - Xh[rows] * ev[None, :]).max()
     say("sampled residual", r, "scale", hn)
     assert r <= 1e-7 * hn
+    # rotational invariance through the same generated-per-element path: J^2 as an interaction
+    import paper_1902_02064_amd as trbl
+    gj = trbl.Model(w.orbits, w.n_prot, w.n_neut, w.twoM, w.parity)
+    gj.set_hamiltonian(jsquared_spe(w.orbits), jsquared_spe(w.orbits), jsquared_tbme(w.orbits))
+    j2 = gj.expect(X)
+    J = (-1 + np.sqrt(1 + 4 * j2)) / 2
+    say("sn112 <J^2>", np.round(j2, 6))
+    assert np.abs(J - np.round(J)).max() <= 1e-5
