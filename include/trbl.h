@@ -136,7 +136,9 @@ int trbl_set_hamiltonian(trbl_model* m, const double* spe_p, const double* spe_n
                          int64_t n_v);
 
 /* W = H V for a block of nb vectors (App. B, on-the-fly block H.V). V, W: device [D][nb],
-   FP64 if precision == TRBL_FP64, FP32 (FP32 accumulation) if TRBL_MIXED. V and W must not alias. */
+   FP64 if precision == TRBL_FP64, FP32 (FP32 accumulation) if TRBL_MIXED. V and W must not alias.
+   For single-species spaces generated per element the model's work blocks are used, so products
+   (and solves) of one such model must not overlap on different streams. */
 int trbl_apply(const trbl_model* m, int precision, int nb, const void* V, void* W, void* stream);
 
 /* Lowest n_eig eigenpairs by TRBL (Alg. 4, Sec. 3.4). evals: host n_eig doubles (ascending).
