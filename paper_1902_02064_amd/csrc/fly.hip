@@ -120,6 +120,9 @@ struct FlyArgs {
   const int2* cd;
   const T* h;
   const T* e;
+  const double* mask;    // optional, Table-1 order: targets with mask 0 get W = 0 without work
+  const int* perm;       // internal -> Table-1 position inside the sector (with mask)
+  const int64_t* soff;   // first M-scheme index of each sector (with mask)
 };
 
 __device__ __forceinline__ int jw_odd(uint64_t w, int s) { return __popcll(w & ((1ull << s) - 1)) & 1; }
@@ -140,6 +143,11 @@ __global__ __launch_bounds__(256) void fly_kernel(FlyArgs<T> a) {
   const int* bk = a.base + ((int64_t)k << a.half);
   const uint64_t w = a.words[t];
   const uint64_t lmask = (1ull << a.half) - 1;
+  if (a.mask && a.mask[a.soff[k] + a.perm[t]] == 0.0) {  // outside a truncated space
+    T* wt = a.W + t * a.nb + c0;
+    for (int c = 0; c < cv; c++) wt[c] = T(0);
+    return;
+  }
   T acc[C];
   T e = T(0);
   for (uint64_t x = w; x; x &= x - 1) e += a.e[__builtin_ctzll(x)];
@@ -198,7 +206,8 @@ __global__ void fly_permute_kernel(const T* src, int64_t lds_, T* dst, int64_t l
 }
 
 template <class T>
-static void run_fly(const Model& m, int nb, const void* V, int64_t ldv, void* W, int64_t ldw, hipStream_t s) {
+static void run_fly(const Model& m, int nb, const void* V, int64_t ldv, void* W, int64_t ldw, const double* mask,
+                    hipStream_t s) {
   FlyArgs<T> a{};
   const int64_t D = m.dim;
   const DeviceTables& d = m.dt;
@@ -226,6 +235,9 @@ static void run_fly(const Model& m, int nb, const void* V, int64_t ldv, void* W,
   a.rank = d.fly_rank.as<int>();
   a.pstart = d.fly_pstart.as<int>();
   a.cd = d.fly_cd.as<int2>();
+  a.mask = mask;
+  a.perm = d.fly_perm.as<int>();
+  a.soff = d.fly_soff.as<int64_t>();
   if constexpr (sizeof(T) == 8) {
     a.h = d.fly_h64.as<T>();
     a.e = d.fly_e64.as<T>();
@@ -245,9 +257,9 @@ static void run_fly(const Model& m, int nb, const void* V, int64_t ldv, void* W,
 }
 
 void launch_fly(const Model& m, int precision, int nb, const void* V, int64_t ldv, void* W, int64_t ldw,
-                hipStream_t s) {
-  if (precision == TRBL_FP64) run_fly<double>(m, nb, V, ldv, W, ldw, s);
-  else run_fly<float>(m, nb, V, ldv, W, ldw, s);
+                hipStream_t s, const double* mask) {
+  if (precision == TRBL_FP64) run_fly<double>(m, nb, V, ldv, W, ldw, mask, s);
+  else run_fly<float>(m, nb, V, ldv, W, ldw, mask, s);
   TRBL_HIP(hipGetLastError());
 }
 

@@ -181,8 +181,9 @@ void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const
 // on-the-fly identical-particle H.V for single-species spaces (fly.hip)
 void build_fly_basis(Model& m);
 void build_fly_terms(Model& m);
+// mask (optional, Table-1 order): rows with mask 0 are set to zero without being generated
 void launch_fly(const Model& m, int precision, int nb, const void* V, int64_t ldv, void* W, int64_t ldw,
-                hipStream_t s);
+                hipStream_t s, const double* mask = nullptr);
 double clebsch(int tj1, int tm1, int tj2, int tm2, int tJ, int tM);
 
 // device launchers (hv.hip)

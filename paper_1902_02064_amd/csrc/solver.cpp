@@ -166,6 +166,13 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
     TRBL_HIP(hipStreamSynchronize(st));
   };
 
+  // H.V of the solve: with a mask on a single-species space generated per element, rows
+  // outside the truncated space are not generated at all (they are zeroed afterwards anyway)
+  auto apply_h = [&](int prec, int ncol, const void* V, int64_t ldv, void* Wo, int64_t ldw) {
+    if (m.fly && o.mask) launch_fly(m, prec, ncol, V, ldv, Wo, ldw, st, o.mask);
+    else launch_apply(m, prec, ncol, V, ldv, Wo, ldw, st);
+  };
+
   // ---- start block V_1 (orthonormalised by Cholesky QR twice)
   if (o.v0)
     copy_cols<TQ, TQ>(static_cast<const TQ*>(o.v0), nb, Q, ldq, D, nb, st);
@@ -208,7 +215,7 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
     TRBL_HIP(hipEventRecord(ev.e[0], st));
     // W := H V_k
     void* Wh = mixed ? (void*)W32 : (void*)W;
-    launch_apply(m, mixed ? TRBL_MIXED : TRBL_FP64, nb, Vk, nb, Wh, nb, st);
+    apply_h(mixed ? TRBL_MIXED : TRBL_FP64, nb, Vk, nb, Wh, nb);
     if (mixed) mask_rows<float>(W32, nb, D, nb, o.mask, st);
     else mask_rows<double>(W, nb, D, nb, o.mask, st);
     TRBL_HIP(hipEventRecord(ev.e[1], st));
@@ -247,7 +254,7 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
     if (sth[0] || sth[1]) {
       // breakdown: W was scaled in place; form it again (same arithmetic) and take the
       // column-wise QR with replacement
-      launch_apply(m, mixed ? TRBL_MIXED : TRBL_FP64, nb, Vk, nb, Wh, nb, st);
+      apply_h(mixed ? TRBL_MIXED : TRBL_FP64, nb, Vk, nb, Wh, nb);
       if (mixed) mask_rows<float>(W32, nb, D, nb, o.mask, st);
       else mask_rows<double>(W, nb, D, nb, o.mask, st);
       if (mixed) {
@@ -375,7 +382,7 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
     for (int c = 0; c < neig; c += cw) {
       const int w = std::min(cw, neig - c);
       copy_cols<TQ, double>(Q + c, ldq, Xc.as<double>(), w, D, w, st);
-      launch_apply(m, TRBL_FP64, w, Xc.as<double>(), w, Hc.as<double>(), w, st);
+      apply_h(TRBL_FP64, w, Xc.as<double>(), w, Hc.as<double>(), w);
       mask_rows<double>(Hc.as<double>(), w, D, w, o.mask, st);
       tn<TQ, double>(Q, ldq, neig, Hc.as<double>(), w, w, D, tmp.as<double>(), sc, st);
       copy_cols<double, double>(tmp.as<double>(), w, S + c, neig, neig, w, st);
@@ -396,7 +403,7 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
       rs.alloc((size_t)neig * sizeof(double));
       for (int c = 0; c < neig; c += cw) {
         const int w = std::min(std::min(cw, 64), neig - c);
-        launch_apply(m, TRBL_FP64, w, X + c, neig, Hc.as<double>(), w, st);
+        apply_h(TRBL_FP64, w, X + c, neig, Hc.as<double>(), w);
         mask_rows<double>(Hc.as<double>(), w, D, w, o.mask, st);
         resid_cols(Hc.as<double>(), w, X + c, neig, th2.as<double>() + c, w, D, rs.as<double>() + c, sc, st);
       }

@@ -70,3 +70,26 @@ def test_truncated_start_block_full_solve():
     assert ir.converged and is_.converged
     assert np.abs(ev_s - ev_r).max() <= 1e-8 * np.abs(ev_r).max()
     assert is_.iterations < ir.iterations
+
+
+def test_truncated_solve_single_species_generated_path():
+    """Single species on the per-element path (forced): rows outside the truncated space are not
+    generated; the masked solve still gives the eigenvalues of the restricted H."""
+    import os
+
+    from workloads import SNSB_ORBITS
+    tb = random_tbme(SNSB_ORBITS, 27)
+    spe = (0.0, 0.2, 1.5, 1.8, 2.4)
+    os.environ["TRBL_FLY"] = "1"
+    try:
+        g, o = pair(SNSB_ORBITS, 0, 4, 0, tb, spe, spe, 1)
+    finally:
+        del os.environ["TRBL_FLY"]
+    mask = g.occupation_mask([2, 3, 4], 1)
+    keep = np.nonzero(mask.cpu().numpy())[0]
+    H = o.dense()
+    et = np.linalg.eigvalsh(H[np.ix_(keep, keep)])
+    ev, X, info = g.solve(4, 5, 12, 32, 1e-10, "fp64", vectors=True, mask=mask)
+    say("single species truncated D", len(keep), "of", g.dim, "max err", np.abs(ev - et[:5]).max())
+    assert info.converged
+    assert np.abs(ev - et[:5]).max() <= 1e-9 * np.abs(et).max()
