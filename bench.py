@@ -11,6 +11,12 @@ are resident in HBM before the timed region.
 Printed: one JSON line. value = seconds per solve in FP64 (lower is better);
 the mixed-precision solve, the H.V kernel's own timing, the roofline of the
 dominant kernel and the CPU oracle baseline are extra fields.
+
+Other modes (one JSON line each, not the benchmark line): --workload sn112 runs the
+same benchmark on the single-species 112Sn shape of Sec. 4.2; --sweep measures the
+block-size trade-off of Sec. 4.2; --truncated-start compares start vectors from a
+particle-hole truncated space with a random start block (Sec. 4.2); --hv-only times
+the block H.V alone (for profilers).
 """
 from __future__ import annotations
 
