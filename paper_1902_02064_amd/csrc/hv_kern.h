@@ -213,13 +213,16 @@ constexpr int hs_bytes(int rbkb) { return rbkb == 36 ? 4096 : 8192; }
 // block (App. B). One lane owns target n' (sectors wider than 1024 are split in chunks) and the C
 // columns of the tile. Its neutron jumps of the current class sit in registers; the class
 // table rows of the proton ops sit in LDS; source rows stream through B0/B1.
-template <class T, int C, int NTB, int RBKB, bool DMA>
+// SB (one row buffer): the current source row is staged and waited for at every step; used
+// for narrow sectors with wide source rows, where half the LDS lets two workgroups share a
+// CU and overlap each other's staging instead of their own.
+template <class T, int C, int NTB, int RBKB, bool DMA, bool SB = false>
 __global__ __launch_bounds__(NTB) void hv_rows_kernel(HVArgs<T> a) {
   constexpr int MAXP = 1;  // targets per lane (wider sectors are split into chunks)
   constexpr int RBYTES = RBKB * 1024;
   constexpr int HSN = hs_bytes(RBKB) / (int)sizeof(T);
   __shared__ __align__(16) char B0[RBYTES];
-  __shared__ __align__(16) char B1[RBYTES];
+  __shared__ __align__(16) char B1[SB ? 16 : RBYTES];
   __shared__ __align__(16) T HS[HSN];
   const int64_t nitems = a.bin_item0[a.bin_nblk];
   const int64_t item = xcd_item(blockIdx.x, nitems);
@@ -257,7 +260,7 @@ __global__ __launch_bounds__(NTB) void hv_rows_kernel(HVArgs<T> a) {
   const int gend = ldu(a.pg_start, gp + 1);
   GroupIt it = group_at(a, b, ldu(a.pg_start, gp), gend);
   stage_row(B0, off + (int64_t)pl * dn, dn);
-  if (it.cls < ncl) stage_row(B1, a.blk_off[it.sb] + (int64_t)it.p * a.blk_dn[it.sb], a.blk_dn[it.sb]);
+  if (!SB && it.cls < ncl) stage_row(B1, a.blk_off[it.sb] + (int64_t)it.p * a.blk_dn[it.sb], a.blk_dn[it.sb]);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 
@@ -315,8 +318,13 @@ __global__ __launch_bounds__(NTB) void hv_rows_kernel(HVArgs<T> a) {
       __syncthreads();
     }
     const GroupIt nx = group_at(a, b, it.g + 1, gend);
-    if (nx.cls < ncl)
+    if constexpr (SB) {  // the only buffer is free (every lane passed the previous barrier)
+      stage_row(B0, ldu(a.blk_off, it.sb) + (int64_t)it.p * ldu(a.blk_dn, it.sb), ldu(a.blk_dn, it.sb));
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    } else if (nx.cls < ncl) {
       stage_row(wr, ldu(a.blk_off, nx.sb) + (int64_t)nx.p * ldu(a.blk_dn, nx.sb), ldu(a.blk_dn, nx.sb));
+    }
     // hr points into LDS or into global memory: two copies of the loop keep every load
     // typed (a generic pointer would make the compiler wait for the DMA in flight).
     // Terms with the same source element are summed before the row is read: in the class of
@@ -371,10 +379,14 @@ __global__ __launch_bounds__(NTB) void hv_rows_kernel(HVArgs<T> a) {
     __syncthreads();
     it = nx;
   };
-  while (it.cls < ncl) {
-    step(B1, B0);
-    if (it.cls >= ncl) break;
-    step(B0, B1);
+  if constexpr (SB) {
+    while (it.cls < ncl) step(B0, B0);
+  } else {
+    while (it.cls < ncl) {
+      step(B1, B0);
+      if (it.cls >= ncl) break;
+      step(B0, B1);
+    }
   }
   using L = Tile<T, C>;
 #pragma unroll
@@ -441,8 +453,9 @@ __global__ __launch_bounds__(1024) void hv_cols_kernel(HVArgs<T> a) {
 template <class T, int C, int NTB, int RB>
 static void launch_rows(const HVArgs<T>& a, const HVBin& B, hipStream_t s) {
   const dim3 grid((unsigned)((B.items + 7) / 8 * 8)), block(B.nthr);
-  if (a.dma) hipLaunchKernelGGL((hv_rows_kernel<T, C, NTB, RB, true>), grid, block, 0, s, a);
-  else hipLaunchKernelGGL((hv_rows_kernel<T, C, NTB, RB, false>), grid, block, 0, s, a);
+  constexpr bool SB = NTB == 256;  // narrow sectors: one buffer, two or more workgroups per CU
+  if (a.dma) hipLaunchKernelGGL((hv_rows_kernel<T, C, NTB, RB, true, SB>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((hv_rows_kernel<T, C, NTB, RB, false, SB>), grid, block, 0, s, a);
 }
 template <class T, int C, int MP>
 static void launch_cols(const HVArgs<T>& a, const HVPlan& P, hipStream_t s) {
