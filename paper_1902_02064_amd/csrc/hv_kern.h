@@ -217,7 +217,7 @@ constexpr int hs_bytes(int rbkb) { return rbkb == 36 ? 4096 : 8192; }
 // for narrow sectors with wide source rows, where half the LDS lets two workgroups share a
 // CU and overlap each other's staging instead of their own.
 template <class T, int C, int NTB, int RBKB, bool DMA, bool SB = false>
-__global__ __launch_bounds__(NTB) void hv_rows_kernel(HVArgs<T> a) {
+__global__ __launch_bounds__(NTB, (NTB == 768 && sizeof(T) == 4 && RBKB <= 36) ? 6 : 1) void hv_rows_kernel(HVArgs<T> a) {
   constexpr int MAXP = 1;  // targets per lane (wider sectors are split into chunks)
   constexpr int RBYTES = RBKB * 1024;
   constexpr int HSN = hs_bytes(RBKB) / (int)sizeof(T);
