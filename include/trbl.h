@@ -11,7 +11,9 @@
  *     two-body matrix elements);
  *   - H applied to a block of vectors on the fly: App. B (identical-particle
  *     two-body jumps; proton-neutron factorisation through one-body jumps);
- *   - eigensolver: Alg. 4 and the thick-restart equations of Sec. 3.4.
+ *   - eigensolver: Alg. 4 and the thick-restart equations of Sec. 3.4;
+ *   - single-species spaces and start vectors from a particle-hole truncated
+ *     space: Sec. 4.2 (trbl_occupation_mask, trbl_opts.mask).
  *
  * Conventions (fixed by this header):
  *   - Single-particle m-states of one species: orbits in the order given,
