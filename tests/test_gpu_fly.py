@@ -124,3 +124,13 @@ def test_sn112_solve_ritz_pairs(sn112):
     J = (-1 + np.sqrt(1 + 4 * j2)) / 2
     say("sn112 <J^2>", np.round(j2, 6))
     assert np.abs(J - np.round(J)).max() <= 1e-5
+
+
+def test_fly_gradient_reports_error():
+    """The gradient contracts the stored identical-particle operator: a space on the per-element
+    path reports an error instead of a wrong answer."""
+    import paper_1902_02064_amd as trbl
+    tb = random_tbme(SD_ORBITS, 28)
+    g, _ = _forced(SD_ORBITS, 0, 4, 0, tb, [0.0, 0.5, 1.0], 0)
+    with pytest.raises(trbl.TrblError):
+        g.tbme_grad(np.ones(2), nb=2, tol=1e-8)

@@ -93,3 +93,18 @@ def test_truncated_solve_single_species_generated_path():
     say("single species truncated D", len(keep), "of", g.dim, "max err", np.abs(ev - et[:5]).max())
     assert info.converged
     assert np.abs(ev - et[:5]).max() <= 1e-9 * np.abs(et).max()
+
+
+def test_truncation_error_paths():
+    """A bad orbit index or bound is rejected; a mask that keeps no state leaves no start vector
+    (breakdown error, no result)."""
+    import paper_1902_02064_amd as trbl
+    w = WORKLOADS["sd22"]
+    g, _ = pair(w.orbits, w.n_prot, w.n_neut, w.twoM, w.tbme(), w.spe, w.spe, oracle=False)
+    with pytest.raises(trbl.TrblError):
+        g.occupation_mask([7], 1)
+    with pytest.raises(trbl.TrblError):
+        g.occupation_mask([0], -1)
+    empty = torch.zeros(g.dim, dtype=torch.float64, device="cuda")
+    with pytest.raises(trbl.TrblError):
+        g.solve(4, 4, 12, 40, 1e-8, "fp64", mask=empty)
