@@ -67,7 +67,17 @@ static HVPlan& plan_for(const Model& m, int nb, size_t elt) {
     B.ntb = kv.first.first;
     B.rb_kb = kv.first.second;
     B.nthr = std::min(1024, (maxdn + 63) / 64 * 64);
-    B.nchunk = (maxdn + B.nthr - 1) / B.nthr;
+    // sectors wider than 1024: 2 or 4 targets per lane, so a staged source row serves up to
+    // 4096 targets (TRBL_HV_MP=1: one target per lane and 1024-wide chunks, for comparison)
+    static const int mp_cap = [] {
+      const char* env = std::getenv("TRBL_HV_MP");
+      return env ? std::max(1, std::atoi(env)) : 4;
+    }();
+    if (B.ntb == 1024 && B.rb_kb == 72 && maxdn > 1024 && mp_cap > 1) {
+      const int want = (maxdn > 2048 && mp_cap >= 4) ? 4 : 2;
+      if (rows_mp_fits((size_t)C * elt, want)) B.mp = want;
+    }
+    B.nchunk = (maxdn + B.nthr * B.mp - 1) / (B.nthr * B.mp);
     std::vector<int64_t> i0(1, 0);
     for (int b : kv.second) i0.push_back(i0.back() + (int64_t)m.blocks[b].dp * P->ntile * B.nchunk);
     B.nblk = (int)kv.second.size();

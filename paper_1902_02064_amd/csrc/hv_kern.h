@@ -205,20 +205,28 @@ __device__ __forceinline__ GroupIt group_at(const HVArgs<T>& a, int b, int g, in
 }
 
 constexpr int MAXE = 8;           // neutron jumps per (target, class) kept in registers
+// A bin with MP > 1 targets per lane holds sectors wider than (MP / 2) * 1024 in its 72 KB row
+// buffer, so its tile rows (C * sizeof(T), a power of two) are at most 128 / MP bytes.
+constexpr bool rows_mp_fits(size_t tile_row_bytes, int mp) { return tile_row_bytes * mp <= 128; }
 // LDS rows of the class table used by the target's proton jumps (smaller with the 36 KB row
 // buffers, so that two workgroups fit in the 160 KB of LDS of a CU)
 constexpr int hs_bytes(int rbkb) { return rbkb == 36 ? 4096 : 8192; }
 
 // Rows kernel: neutron-neutron and proton-neutron parts of W for one proton row p' of one
-// block (App. B). One lane owns target n' (sectors wider than 1024 are split in chunks) and the C
+// block (App. B). One lane owns target n' (or MP of them; wider sectors are split in chunks) and the C
 // columns of the tile. Its neutron jumps of the current class sit in registers; the class
 // table rows of the proton ops sit in LDS; source rows stream through B0/B1.
 // SB (one row buffer): the current source row is staged and waited for at every step; used
 // for narrow sectors with wide source rows, where half the LDS lets two workgroups share a
 // CU and overlap each other's staging instead of their own.
-template <class T, int C, int NTB, int RBKB, bool DMA, bool SB = false>
+// MP (targets per lane): sectors wider than 1024 give each lane MP targets n', n' + 1024, ...,
+// so that a staged source row serves the whole sector instead of one 1024-wide chunk of it.
+template <class T, int C, int NTB, int RBKB, bool DMA, bool SB = false, int MP = 1>
 __global__ __launch_bounds__(NTB, (NTB == 768 && sizeof(T) == 4 && RBKB <= 36) ? 6 : 1) void hv_rows_kernel(HVArgs<T> a) {
-  constexpr int MAXP = 1;  // targets per lane (wider sectors are split into chunks)
+  constexpr int MAXP = MP;  // targets per lane (sectors wider than MP * 1024 are split into chunks)
+  // neutron jumps per (target, class) in registers: fewer with 4 targets per lane (the rest are
+  // read from the table as they are used)
+  constexpr int NE = MP >= 4 ? 4 : MAXE;
   constexpr int RBYTES = RBKB * 1024;
   constexpr int HSN = hs_bytes(RBKB) / (int)sizeof(T);
   __shared__ __align__(16) char B0[RBYTES];
@@ -281,7 +289,7 @@ __global__ __launch_bounds__(NTB, (NTB == 768 && sizeof(T) == 4 && RBKB <= 36) ?
   __syncthreads();
 
   // proton-neutron part
-  int2 er[MAXP][MAXE];
+  int2 er[MAXP][NE];
   int eb[MAXP], ec[MAXP];
   int cur = -1, j0c = 0, hn = 0;
   bool hs_lds = false;
@@ -297,7 +305,7 @@ __global__ __launch_bounds__(NTB, (NTB == 768 && sizeof(T) == 4 && RBKB <= 36) ?
         eb[q] = n < thi ? ns0[n] : 0;
         ec[q] = n < thi ? ns0[n + 1] - eb[q] : 0;
 #pragma unroll
-        for (int i = 0; i < MAXE; i++) {
+        for (int i = 0; i < NE; i++) {
           er[q][i] = make_int2(0, 0);
           if (i < ec[q]) er[q][i] = a.nj_pack[eb[q] + i];
           // pin the loads here (before the barrier and the next DMA), not next to their first use
@@ -339,14 +347,14 @@ __global__ __launch_bounds__(NTB, (NTB == 768 && sizeof(T) == 4 && RBKB <= 36) ?
           if (nm > 0 && ec[q] >= nm) {
             T sum = T(0);
 #pragma unroll
-            for (int i = 0; i < MAXE; i++)
+            for (int i = 0; i < NE; i++)
               if (i < nm) sum += cf(er[q][i]);
             gather<T, C>(acc[q], sum, rd, er[q][0].x, rot);
           }
 #pragma unroll
-          for (int i = 0; i < MAXE; i++)
+          for (int i = 0; i < NE; i++)
             if (i >= nm && i < ec[q]) gather<T, C>(acc[q], cf(er[q][i]), rd, er[q][i].x, rot);
-          for (int i = MAXE; i < ec[q]; i++) {
+          for (int i = NE; i < ec[q]; i++) {
             const int2 e = a.nj_pack[eb[q] + i];
             gather<T, C>(acc[q], cf(e), rd, e.x, rot);
           }
@@ -450,12 +458,12 @@ __global__ __launch_bounds__(1024) void hv_cols_kernel(HVArgs<T> a) {
   }
 }
 
-template <class T, int C, int NTB, int RB>
+template <class T, int C, int NTB, int RB, int MP = 1>
 static void launch_rows(const HVArgs<T>& a, const HVBin& B, hipStream_t s) {
   const dim3 grid((unsigned)((B.items + 7) / 8 * 8)), block(B.nthr);
   constexpr bool SB = NTB == 256;  // narrow sectors: one buffer, two or more workgroups per CU
-  if (a.dma) hipLaunchKernelGGL((hv_rows_kernel<T, C, NTB, RB, true, SB>), grid, block, 0, s, a);
-  else hipLaunchKernelGGL((hv_rows_kernel<T, C, NTB, RB, false, SB>), grid, block, 0, s, a);
+  if (a.dma) hipLaunchKernelGGL((hv_rows_kernel<T, C, NTB, RB, true, SB, MP>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((hv_rows_kernel<T, C, NTB, RB, false, SB, MP>), grid, block, 0, s, a);
 }
 template <class T, int C, int MP>
 static void launch_cols(const HVArgs<T>& a, const HVPlan& P, hipStream_t s) {
@@ -476,7 +484,13 @@ static void dispatch_c(HVArgs<T>& a, const HVPlan& P, hipStream_t s) {
                  : B.rb_kb == 36 ? launch_rows<T, C, NTB, 36>(a, B, s) : launch_rows<T, C, NTB, 72>(a, B, s))
     if (B.ntb == 256) TRBL_ROWS_RB(256);
     else if (B.ntb == 768) TRBL_ROWS_RB(768);
-    else TRBL_ROWS_RB(1024);
+    else if (B.mp == 4) {
+      if constexpr (rows_mp_fits(C * sizeof(T), 4)) launch_rows<T, C, 1024, 72, 4>(a, B, s);
+      else TRBL_REQUIRE(false, TRBL_E_INVALID, "targets-per-lane plan does not match the column tile");
+    } else if (B.mp == 2) {
+      if constexpr (rows_mp_fits(C * sizeof(T), 2)) launch_rows<T, C, 1024, 72, 2>(a, B, s);
+      else TRBL_REQUIRE(false, TRBL_E_INVALID, "targets-per-lane plan does not match the column tile");
+    } else TRBL_ROWS_RB(1024);
 #undef TRBL_ROWS_RB
   }
   a.nchunk = P.nchunk_c;

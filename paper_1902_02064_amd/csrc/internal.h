@@ -123,6 +123,7 @@ struct DeviceTables {
 // reservation and the workgroup width fit the sector.
 struct HVBin {
   int nthr = 64, ntb = 256, nchunk = 1, rb_kb = 24, nblk = 0;  // width, its launch bound, chunks, LDS row KB
+  int mp = 1;                                                    // targets per lane (1024-wide, 72 KB bins)
   int64_t items = 0;
   DevBuf blocks, item0;  // block ids of the bin, first work item of each (nblk + 1)
 };
