@@ -32,10 +32,12 @@ void apply_small(const TI* Bin, int64_t ldi, const double* R, TO* Bout, int64_t 
 // Cholesky of the sum of G partial nb x nb Gram matrices: R, R^-1, beta = R Rprev (if beta), status.
 void chol(const double* part, int G, int nb, double* R, double* Rinv, const double* Rprev, double* beta, int* status,
           hipStream_t st);
-// Y[:, 0:ncol] = A[:, 0:m] U (row-wise, in place allowed); then optional column block move.
+// Y[:, 0:ncol] = A[:, 0:m] U (row-wise, in place allowed); then optional column block move
+// (columns [vsrc, vsrc+nv) of A to [vdst, vdst+nv) of Y). In place with ncol > 208 needs a work
+// buffer tmp of tmp_elems >= ncol + nv elements (rows go through it in chunks; vdst >= ncol).
 template <class TA, class TY>
 void rowgemm(const TA* A, int64_t lda, int m, const double* U, int64_t ldu, int ncol, TY* Y, int64_t ldy, int64_t D,
-             int vsrc, int vdst, int nv, hipStream_t st);
+             int vsrc, int vdst, int nv, hipStream_t st, TY* tmp = nullptr, int64_t tmp_elems = 0);
 template <class T>
 void random_block(T* out, int64_t ld, int64_t D, int nb, uint64_t seed, hipStream_t st);
 template <class TS, class TD>

@@ -871,7 +871,7 @@ void chol(const double* part, int G, int nb, double* R, double* Rinv, const doub
 
 template <class TA, class TY>
 void rowgemm(const TA* A, int64_t lda, int m, const double* U, int64_t ldu, int ncol, TY* Y, int64_t ldy, int64_t D,
-             int vsrc, int vdst, int nv, hipStream_t st) {
+             int vsrc, int vdst, int nv, hipStream_t st, TY* tmp, int64_t tmp_elems) {
   const int G = grid_for(D, 128, 2048);
   const int nt = (ncol + 15) / 16;
   auto shm = [&](int NT) { return (size_t)(2 * 16 * NT * 16 + 128 * std::max(nv, 1)) * sizeof(double); };
@@ -885,12 +885,37 @@ void rowgemm(const TA* A, int64_t lda, int m, const double* U, int64_t ldu, int 
     hipLaunchKernelGGL((rowgemm_kernel<TA, TY, 13>), dim3(G), dim3(512), shm(13), st, A, lda, m, U, ldu, ncol, Y,
                        ldy, D, vsrc, vdst, nv);
   else {
-    // wide outputs: column groups of 13 tiles; only valid out of place
-    TRBL_REQUIRE((const void*)A != (const void*)Y || vsrc < 0, TRBL_E_INVALID, "in-place rowgemm too wide");
-    for (int c0 = 0; c0 < ncol; c0 += 13 * 16) {
-      const int nc = std::min(13 * 16, ncol - c0);
-      hipLaunchKernelGGL((rowgemm_kernel<TA, TY, 13>), dim3(G), dim3(512), shm(13), st, A, lda, m, U + c0, ldu, nc,
-                         Y + c0, ldy, D, -1, 0, 0);
+    // wide outputs: column groups of 13 tiles. In place, a group would overwrite columns that the
+    // next group still reads, so rows go through tmp in chunks: each chunk is computed out of
+    // place, then copied back with its part of the moved block before the next chunk is read.
+    auto groups = [&](const TA* a, TY* y, int64_t ly, int64_t rows) {
+      const int g = grid_for(rows, 128, 2048);
+      for (int c0 = 0; c0 < ncol; c0 += 13 * 16) {
+        const int nc = std::min(13 * 16, ncol - c0);
+        hipLaunchKernelGGL((rowgemm_kernel<TA, TY, 13>), dim3(g), dim3(512), shm(13), st, a, lda, m, U + c0, ldu, nc,
+                           y + c0, ly, rows, -1, 0, 0);
+      }
+    };
+    if ((const void*)A != (const void*)Y) {
+      groups(A, Y, ldy, D);
+      if (vsrc >= 0) copy_cols<TA, TY>(A + vsrc, lda, Y + vdst, ldy, D, nv, st);
+    } else {
+      // the moved block of a chunk is parked in tmp too (its source and destination may overlap)
+      const int nvv = vsrc >= 0 ? nv : 0;
+      TRBL_REQUIRE(tmp && tmp_elems >= (int64_t)(ncol + nvv), TRBL_E_INVALID,
+                   "in-place product wider than 208 columns needs a work buffer");
+      TRBL_REQUIRE(vsrc < 0 || vdst >= ncol, TRBL_E_INVALID, "moved block inside the product's columns");
+      int64_t chunk = tmp_elems / (ncol + nvv);
+      if (chunk >= 128) chunk = chunk / 128 * 128;  // whole row tiles of the kernel
+      chunk = std::min<int64_t>(D, chunk);
+      TY* tv = tmp + chunk * ncol;
+      for (int64_t r0 = 0; r0 < D; r0 += chunk) {
+        const int64_t rows = std::min(chunk, D - r0);
+        groups(A + r0 * lda, tmp, ncol, rows);
+        if (nvv) copy_cols<TA, TY>(A + r0 * lda + vsrc, lda, tv, nv, rows, nv, st);
+        copy_cols<TY, TY>(tmp, ncol, Y + r0 * ldy, ldy, rows, ncol, st);
+        if (nvv) copy_cols<TY, TY>(tv, nv, Y + r0 * ldy + vdst, ldy, rows, nv, st);
+      }
     }
   }
   TRBL_HIP(hipGetLastError());
@@ -964,11 +989,11 @@ template void apply_small<double, float>(const double*, int64_t, const double*, 
 template void apply_small<float, double>(const float*, int64_t, const double*, double*, int64_t, int, int64_t, bool,
                                          Scratch&, hipStream_t);
 template void rowgemm<double, double>(const double*, int64_t, int, const double*, int64_t, int, double*, int64_t,
-                                      int64_t, int, int, int, hipStream_t);
+                                      int64_t, int, int, int, hipStream_t, double*, int64_t);
 template void rowgemm<float, float>(const float*, int64_t, int, const double*, int64_t, int, float*, int64_t, int64_t,
-                                    int, int, int, hipStream_t);
+                                    int, int, int, hipStream_t, float*, int64_t);
 template void rowgemm<float, double>(const float*, int64_t, int, const double*, int64_t, int, double*, int64_t,
-                                     int64_t, int, int, int, hipStream_t);
+                                     int64_t, int, int, int, hipStream_t, double*, int64_t);
 template void random_block<double>(double*, int64_t, int64_t, int, uint64_t, hipStream_t);
 template void random_block<float>(float*, int64_t, int64_t, int, uint64_t, hipStream_t);
 template void mask_rows<double>(double*, int64_t, int64_t, int, const double*, hipStream_t);

@@ -339,7 +339,9 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
     }
     if (restart_next && it < o.max_iter) {
       TRBL_HIP(hipEventRecord(ev.e[4], st));
-      rowgemm<TQ, TQ>(Q, ldq, mcur, U, ldu, ls, Q, ldq, D, mcur, ls, nb, st);
+      // W is free between iterations: the work buffer of restarts that keep more than 208 vectors
+      rowgemm<TQ, TQ>(Q, ldq, mcur, U, ldu, ls, Q, ldq, D, mcur, ls, nb, st, reinterpret_cast<TQ*>(W),
+                      D * nb * (int64_t)(sizeof(double) / sizeof(TQ)));
       t_restart(T, lm, lm, theta, ls, beta, nb, U, ldu, mcur, st);
       TRBL_HIP(hipEventRecord(ev.e[5], st));
       TRBL_HIP(hipEventSynchronize(ev.e[5]));

@@ -1,5 +1,6 @@
-"""Full-size solves (GPU): sd66 and pf44 against the oracle TRBL's stored eigenvalues, and the
-mixed-precision pf44 solve against the FP64 one."""
+"""Full-size solves (GPU): sd66 and pf44 against the oracle TRBL's stored eigenvalues (sd66 also
+with restarts that keep more than 208 vectors), and the mixed-precision pf44 solve against the
+FP64 one."""
 import os
 
 import numpy as np
@@ -46,6 +47,28 @@ def test_sd66_matches_oracle_trbl():
     rel = np.abs(ev - ref) / np.abs(ref)
     say("sd66 max rel err", rel.max(), "iterations", info.iterations)
     assert rel.max() <= 1e-8
+
+
+@pytest.mark.parametrize("l_s,l_m", [(216, 232), (220, 236)])
+def test_sd66_restart_keeps_more_than_208_vectors(l_s, l_m):
+    """Thick restarts that keep more than 208 vectors: the restart product Q U is then computed
+    in place by row chunks through a work buffer. With (220, 236) and nb = 8 the block moved to
+    column l_s at the first restart (from column 224) overlaps its destination. FP64 against the
+    oracle TRBL's eigenvalues (<= 1e-8 relative), mixed precision <= 1e-6."""
+    ref = _golden("sd66")
+    w = WORKLOADS["sd66"]
+    g = _model(w)
+    ev, _, info = g.solve(w.nb, w.n_eig, l_s, l_m, w.tol, "fp64", check_every=-1)
+    rel = np.abs(ev - ref) / np.abs(ref)
+    say("sd66 l_s", l_s, "l_m", l_m, "fp64", info.iterations, "iterations", info.restarts, "restarts, max rel err",
+        rel.max())
+    assert info.converged and info.restarts >= 1
+    assert rel.max() <= 1e-8
+    evm, _, im = g.solve(w.nb, w.n_eig, l_s, l_m, w.tol, "mixed", check_every=-1)
+    relm = np.abs(evm - ref) / np.abs(ref)
+    say("mixed", im.iterations, "iterations", im.restarts, "restarts, max rel err", relm.max())
+    assert im.converged and im.restarts >= 1
+    assert relm.max() <= 1e-6
 
 
 def test_pf44_fp64_matches_oracle_trbl(pf44):
