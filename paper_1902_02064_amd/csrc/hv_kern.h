@@ -354,7 +354,18 @@ __global__ __launch_bounds__(NTB, (NTB == 768 && sizeof(T) == 4 && RBKB <= 36) ?
 #pragma unroll
           for (int i = 0; i < NE; i++)
             if (i >= nm && i < ec[q]) gather<T, C>(acc[q], cf(er[q][i]), rd, er[q][i].x, rot);
-          for (int i = NE; i < ec[q]; i++) {
+          // jumps beyond the register-held ones; with narrow tiles (wide sectors, where most jumps
+          // land here) four table loads are put in flight before their gathers
+          int i = NE;
+          if constexpr (C * sizeof(T) <= 32)
+            for (; i + 4 <= ec[q]; i += 4) {
+              int2 e[4];
+#pragma unroll
+              for (int u = 0; u < 4; u++) e[u] = a.nj_pack[eb[q] + i + u];
+#pragma unroll
+              for (int u = 0; u < 4; u++) gather<T, C>(acc[q], cf(e[u]), rd, e[u].x, rot);
+            }
+          for (; i < ec[q]; i++) {
             const int2 e = a.nj_pack[eb[q] + i];
             gather<T, C>(acc[q], cf(e), rd, e.x, rot);
           }
