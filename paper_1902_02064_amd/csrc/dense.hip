@@ -663,30 +663,30 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t counter) 
 
 template <class T>
 __global__ void random_kernel(T* out, int64_t ld, int64_t D, int nb, uint64_t seed) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= D * nb) return;
-  const uint64_t k = (uint64_t)e;
-  const double u1 = ((double)(splitmix64(seed, 2 * k) >> 11) + 1.0) * (1.0 / 9007199254740992.0);
-  const double u2 = ((double)(splitmix64(seed, 2 * k + 1) >> 11) + 1.0) * (1.0 / 9007199254740992.0);
-  const double z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
-  out[(e / nb) * ld + e % nb] = (T)z;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < D * nb; e += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = (uint64_t)e;
+    const double u1 = ((double)(splitmix64(seed, 2 * k) >> 11) + 1.0) * (1.0 / 9007199254740992.0);
+    const double u2 = ((double)(splitmix64(seed, 2 * k + 1) >> 11) + 1.0) * (1.0 / 9007199254740992.0);
+    const double z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+    out[(e / nb) * ld + e % nb] = (T)z;
+  }
 }
 
 template <class T>
 __global__ void mask_rows_kernel(T* X, int64_t ld, int64_t D, int ncol, const double* __restrict__ mask) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= D * ncol) return;
-  const int64_t r = e / ncol;
-  if (mask[r] == 0.0) X[r * ld + (e - r * ncol)] = T(0);
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < D * ncol; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / ncol;
+    if (mask[r] == 0.0) X[r * ld + (e - r * ncol)] = T(0);
+  }
 }
 
 template <class TS, class TD>
 __global__ void copy_cols_kernel(const TS* src, int64_t lds_, TD* dst, int64_t ldd, int64_t D, int ncol) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= D * ncol) return;
-  const int64_t r = e / ncol;
-  const int c = (int)(e % ncol);
-  dst[r * ldd + c] = (TD)src[r * lds_ + c];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < D * ncol; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / ncol;
+    const int c = (int)(e % ncol);
+    dst[r * ldd + c] = (TD)src[r * lds_ + c];
+  }
 }
 
 // T-matrix bookkeeping of Alg. 4 (device-resident T, leading dimension ldt)
@@ -924,7 +924,7 @@ void rowgemm(const TA* A, int64_t lda, int m, const double* U, int64_t ldu, int 
 template <class T>
 void random_block(T* out, int64_t ld, int64_t D, int nb, uint64_t seed, hipStream_t st) {
   const int64_t n = D * nb;
-  hipLaunchKernelGGL(random_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, out, ld, D, nb, seed);
+  hipLaunchKernelGGL(random_kernel<T>, dim3(elementwise_grid(n)), dim3(256), 0, st, out, ld, D, nb, seed);
   TRBL_HIP(hipGetLastError());
 }
 
@@ -932,15 +932,15 @@ template <class T>
 void mask_rows(T* X, int64_t ld, int64_t D, int ncol, const double* mask, hipStream_t st) {
   if (!mask) return;
   const int64_t n = D * ncol;
-  hipLaunchKernelGGL(mask_rows_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, X, ld, D, ncol, mask);
+  hipLaunchKernelGGL(mask_rows_kernel<T>, dim3(elementwise_grid(n)), dim3(256), 0, st, X, ld, D, ncol, mask);
   TRBL_HIP(hipGetLastError());
 }
 
 template <class TS, class TD>
 void copy_cols(const TS* src, int64_t lds_, TD* dst, int64_t ldd, int64_t D, int ncol, hipStream_t st) {
   const int64_t n = D * ncol;
-  hipLaunchKernelGGL((copy_cols_kernel<TS, TD>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, lds_, dst,
-                     ldd, D, ncol);
+  hipLaunchKernelGGL((copy_cols_kernel<TS, TD>), dim3(elementwise_grid(n)), dim3(256), 0, st, src, lds_, dst, ldd, D,
+                     ncol);
   TRBL_HIP(hipGetLastError());
 }
 

@@ -194,15 +194,15 @@ __global__ __launch_bounds__(256) void fly_kernel(FlyArgs<T> a) {
 template <class T>
 __global__ void fly_permute_kernel(const T* src, int64_t lds_, T* dst, int64_t ldd, int nb, int64_t n, int nsec,
                                    const int* sstart, const int64_t* soff, const int* perm, int to_internal) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= n * nb) return;
-  const int64_t i = e / nb;
-  const int c = (int)(e - i * nb);
-  int k = 0;
-  while (k + 1 < nsec && i >= sstart[k + 1]) k++;
-  const int64_t row = soff[k] + perm[i];
-  if (to_internal) dst[i * ldd + c] = src[row * lds_ + c];
-  else dst[row * ldd + c] = src[i * lds_ + c];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * nb; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / nb;
+    const int c = (int)(e - i * nb);
+    int k = 0;
+    while (k + 1 < nsec && i >= sstart[k + 1]) k++;
+    const int64_t row = soff[k] + perm[i];
+    if (to_internal) dst[i * ldd + c] = src[row * lds_ + c];
+    else dst[row * ldd + c] = src[i * lds_ + c];
+  }
 }
 
 template <class T>
@@ -218,7 +218,7 @@ static void run_fly(const Model& m, int nb, const void* V, int64_t ldv, void* W,
   T* win = vin + D * nb;
   const int nsec = (int)m.sp[m.fly_s].sectors.size();
   const int64_t ne = D * nb;
-  const unsigned g1 = (unsigned)((ne + 255) / 256);
+  const unsigned g1 = elementwise_grid(ne);
   hipLaunchKernelGGL((fly_permute_kernel<T>), dim3(g1), dim3(256), 0, s, static_cast<const T*>(V), ldv, vin,
                      (int64_t)nb, nb, D, nsec, d.fly_sstart.as<int>(), d.fly_soff.as<int64_t>(),
                      d.fly_perm.as<int>(), 1);

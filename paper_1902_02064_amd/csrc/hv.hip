@@ -82,7 +82,8 @@ static HVPlan& plan_for(const Model& m, int nb, size_t elt) {
     for (int b : kv.second) i0.push_back(i0.back() + (int64_t)m.blocks[b].dp * P->ntile * B.nchunk);
     B.nblk = (int)kv.second.size();
     B.items = i0.back();
-    TRBL_REQUIRE(B.items < (int64_t)1 << 31, TRBL_E_INVALID, "problem too large for one launch");
+    TRBL_REQUIRE(B.items < (int64_t)1 << 31 && (B.items + 7) * B.nthr < (int64_t)1 << 32, TRBL_E_INVALID,
+                 "problem too large for one launch");
     B.blocks.upload(kv.second);
     B.item0.upload(i0);
   }
@@ -95,7 +96,8 @@ static HVPlan& plan_for(const Model& m, int nb, size_t elt) {
   for (size_t b = 0; b < m.blocks.size(); b++)
     c0[b + 1] = c0[b] + (int64_t)m.blocks[b].dn * P->ntile * P->nchunk_c;
   P->cols_items = c0.back();
-  TRBL_REQUIRE(P->cols_items < (int64_t)1 << 31, TRBL_E_INVALID, "problem too large for one launch");
+  TRBL_REQUIRE(P->cols_items < (int64_t)1 << 31 && (P->cols_items + 7) * P->nthr_c < (int64_t)1 << 32,
+               TRBL_E_INVALID, "problem too large for one launch");
   P->citem0.upload(c0);
   P->shm_c = ((size_t)m.max_dp * rs_of(C, elt) * elt + 15) / 16 * 16;
   m.hv_plans[key] = std::move(owned);

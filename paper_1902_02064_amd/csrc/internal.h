@@ -30,6 +30,14 @@ void set_error(const std::string& msg);
     if (!(cond)) throw ::trbl::Error{(code), (msg)};      \
   } while (0)
 
+// Blocks of 256 lanes for a grid-stride loop over n elements. A dispatch describes its size in
+// 32-bit work-item counts, so one lane per element would wrap beyond 2^32 elements (a D x 384
+// block of a 1e8-dimensional space); the cap keeps every launch far below that.
+inline unsigned elementwise_grid(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return (unsigned)(b < 1 ? 1 : b > (1 << 20) ? (1 << 20) : b);
+}
+
 // ---------------------------------------------------------------- device buffer
 struct DevBuf {
   void* p = nullptr;
