@@ -364,8 +364,8 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
   } else {
     // FP64 Rayleigh-Ritz on span(X), X = Q U[:, :n_eig] stored in place in Q's first n_eig columns
     TRBL_HIP(hipEventRecord(ev.e[0], st));
-    TRBL_REQUIRE(neig <= 208, TRBL_E_INVALID, "refinement supports n_eig <= 208");
-    rowgemm<TQ, TQ>(Q, ldq, mcur, U, ldu, neig, Q, ldq, D, -1, 0, 0, st);
+    rowgemm<TQ, TQ>(Q, ldq, mcur, U, ldu, neig, Q, ldq, D, -1, 0, 0, st, reinterpret_cast<TQ*>(W),
+                    D * nb * (int64_t)(sizeof(double) / sizeof(TQ)));
     const int cw = (int)std::max<int64_t>(1, std::min<int64_t>(32, (int64_t)(8e9 / (16.0 * D))));
     DevBuf Xc, Hc, Sb, Gb, Mb, Lb, Yb, Yp, tmp, th2, st2;
     Xc.alloc((size_t)D * cw * sizeof(double));

@@ -58,6 +58,21 @@ def test_mixed_matches_oracle_sd22(sd22):
     assert np.abs(Xh.T @ Xh - np.eye(w.n_eig)).max() < 1e-8
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_more_than_208_eigenpairs(sd22, prec):
+    """220 of the 640 eigenvalues, keeping 240 vectors at a restart: the in-place restart product
+    and (mixed) the refinement's in-place Ritz-vector product are wider than one workgroup's 208
+    columns and go through the work buffer in row chunks (here smaller than a 128-row tile)."""
+    w, g, o, H, e = sd22
+    ev, X, info = g.solve(4, 220, 240, 300, 1e-9, prec, vectors=True, check_every=-1)
+    rel = np.abs(ev - e[:220]) / np.abs(e[:220])
+    say(prec, "220 eigenpairs", info.iterations, "iterations", info.restarts, "restarts, max rel err", rel.max())
+    assert info.converged and info.restarts >= 1
+    assert rel.max() <= (1e-8 if prec == "fp64" else 1e-6)
+    Xh = X.cpu().numpy()
+    assert np.abs(Xh.T @ Xh - np.eye(220)).max() < 1e-8
+
+
 @pytest.mark.parametrize("nb,ls,lm,neig", [(1, 8, 40, 6), (2, 12, 30, 8), (8, 16, 64, 10), (16, 40, 120, 30)])
 def test_block_sizes_and_restart_shapes(sd22, nb, ls, lm, neig):
     w, g, o, H, e = sd22
