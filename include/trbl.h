@@ -149,7 +149,11 @@ int trbl_apply(const trbl_model* m, int precision, int nb, const void* V, void* 
    (start block with dependent columns, Krylov space exhausted) is factored column by column
    and its deficient columns are replaced by random vectors orthogonal to the basis
    (info->breakdowns counts them). Device memory: the basis [D][round4(l_m)] in FP64 (or FP32
-   with TRBL_MIXED), one FP64 [D][nb] block (plus an FP32 one in mixed mode), small tables.
+   with TRBL_MIXED), a packed copy of the current block [D][nb] in the basis precision, one
+   FP64 [D][nb] block (plus an FP32 one in mixed mode; the FP64 one also serves as the work
+   buffer of restarts that keep more than 208 vectors), small tables; the mixed refinement
+   adds two FP64 [D][w] blocks, w = max(1, min(32, 5e8 / D)) columns (at most 8 GB together
+   while D <= 5e8).
    Returns TRBL_NOT_CONVERGED after max_iter iterations with the current Ritz values (NaN
    beyond the m available when fewer than n_eig exist yet). */
 int trbl_solve(const trbl_model* m, const trbl_opts* opts, double* evals, void* evecs, trbl_info* info);
