@@ -118,6 +118,22 @@ def test_pf66_mixed_restart_and_refinement():
     assert d <= 1e-4 * np.abs(e0).max()
 
 
+def test_pf66_fp64_vs_mixed_same_start():
+    """pf shell 6+6 has no CPU oracle run; its precision parity is GPU FP64 against GPU mixed.
+    nb = 32, 8 wanted, l_s = 64, l_m = 128 (the FP64 basis then fits: 113 GB), 12 iterations
+    (9 restarts) from the same start block: the 8 lowest values, mixed with its FP64 refinement,
+    agree with FP64 to <= 1e-6 relative."""
+    w = WORKLOADS["pf66"]
+    g = _model(w)
+    say("pf66 fp64 and mixed, 12 iterations")
+    e64, _, i64 = g.solve(32, 8, 64, 128, 1e-5, "fp64", max_iter=12, check_every=1, seed=1000)
+    e32, _, i32 = g.solve(32, 8, 64, 128, 1e-5, "mixed", max_iter=12, check_every=1, seed=1000)
+    rel = np.abs(e32 - e64) / np.abs(e64)
+    say("pf66 fp64", e64[:4], "mixed max rel", rel.max(), "t", i64.t_total, i32.t_total)
+    assert i64.iterations == i32.iterations == 12 and i64.restarts == i32.restarts >= 1
+    assert rel.max() <= 1e-6
+
+
 def test_pf44_ritz_vectors_have_integer_j():
     """pf44 at full size: <J^2> of the 100 Ritz vectors is J(J+1) with integer J."""
     from workloads import jsquared_spe, jsquared_tbme
