@@ -19,8 +19,10 @@ static int pow2ceil(int x) {
 
 static int rs_of(int C, size_t elt) { return elt == 8 ? (C >= 2 ? C + 2 : 2) : (C >= 4 ? C + 4 : 4); }
 
-// LDS bytes per row buffer of the rows kernel: 24 KB and 36 KB leave room for two workgroups per CU
-constexpr size_t ROW_SMALL = 24 * 1024, ROW_MID = 36 * 1024, ROW_LARGE = 72 * 1024;
+// LDS bytes per row buffer of the rows kernel: 24 KB and 36 KB leave room for two workgroups per
+// CU; 144 KB is one buffer (staged and waited for at each step) for the widest source rows, so
+// that 3,952-wide sectors take a 4-column FP64 (8-column FP32) tile instead of half that
+constexpr size_t ROW_SMALL = 24 * 1024, ROW_MID = 36 * 1024, ROW_LARGE = 72 * 1024, ROW_XL = 144 * 1024;
 
 static HVPlan& plan_for(const Model& m, int nb, size_t elt) {
   const int key = nb * 16 + (int)elt;
@@ -35,12 +37,20 @@ static HVPlan& plan_for(const Model& m, int nb, size_t elt) {
     C = std::max(cmin, std::min(C, std::atoi(env)));
     while (C & (C - 1)) C &= C - 1;
   }
-  while (C > cmin && (size_t)m.max_dn * C * elt > ROW_LARGE) C >>= 1;
-  TRBL_REQUIRE((size_t)m.max_dn * C * elt <= ROW_LARGE, TRBL_E_INVALID, "neutron sector too large for the LDS row tile");
-  TRBL_REQUIRE((size_t)m.max_dp * rs_of(C, elt) * elt <= 144 * 1024, TRBL_E_INVALID,
+  // TRBL_HV_XL=0: tiles sized for the 72 KB double buffer only, for comparison
+  static const size_t row_cap =
+      std::getenv("TRBL_HV_XL") && std::atoi(std::getenv("TRBL_HV_XL")) == 0 ? ROW_LARGE : ROW_XL;
+  while (C > cmin && (size_t)m.max_dn * C * elt > row_cap) C >>= 1;
+  TRBL_REQUIRE((size_t)m.max_dn * C * elt <= row_cap, TRBL_E_INVALID, "neutron sector too large for the LDS row tile");
+  // the columns kernel stages whole proton columns: its own, possibly narrower, tile
+  int Cc = C;
+  while (Cc > cmin && (size_t)m.max_dp * rs_of(Cc, elt) * elt > 144 * 1024) Cc >>= 1;
+  TRBL_REQUIRE((size_t)m.max_dp * rs_of(Cc, elt) * elt <= 144 * 1024 && Cc * 4 >= C, TRBL_E_INVALID,
                "proton sector too large for the LDS column tile");
   P->C = C;
   P->ntile = (nb + C - 1) / C;
+  P->Cc = Cc;
+  P->ntile_c = (nb + Cc - 1) / Cc;
   // rows kernel: one launch per (launch bound, row buffer) class of blocks. The row buffer
   // must hold the widest source row a block's proton jumps can reach.
   const int ncl = m.cl.nclass;
@@ -56,7 +66,7 @@ static HVPlan& plan_for(const Model& m, int nb, size_t elt) {
     const int nthr = std::min(1024, (dn + 63) / 64 * 64);
     const int ntb = nthr <= 256 ? 256 : nthr <= 768 ? 768 : 1024;
     const size_t need = (size_t)widest * C * elt;
-    const int rb = need <= ROW_SMALL ? 24 : need <= ROW_MID ? 36 : 72;
+    const int rb = need <= ROW_SMALL ? 24 : need <= ROW_MID ? 36 : need <= ROW_LARGE ? 72 : 144;
     members[{ntb, rb}].push_back((int)b);
   }
   for (auto& kv : members) {
@@ -73,7 +83,7 @@ static HVPlan& plan_for(const Model& m, int nb, size_t elt) {
       const char* env = std::getenv("TRBL_HV_MP");
       return env ? std::max(1, std::atoi(env)) : 4;
     }();
-    if (B.ntb == 1024 && B.rb_kb == 72 && maxdn > 1024 && mp_cap > 1) {
+    if (B.ntb == 1024 && B.rb_kb >= 72 && maxdn > 1024 && mp_cap > 1) {
       const int want = (maxdn > 2048 && mp_cap >= 4) ? 4 : 2;
       if (rows_mp_fits((size_t)C * elt, want)) B.mp = want;
     }
@@ -94,12 +104,12 @@ static HVPlan& plan_for(const Model& m, int nb, size_t elt) {
   P->nchunk_c = (m.max_dp + P->nthr_c * P->maxp_c - 1) / (P->nthr_c * P->maxp_c);
   std::vector<int64_t> c0(m.blocks.size() + 1, 0);
   for (size_t b = 0; b < m.blocks.size(); b++)
-    c0[b + 1] = c0[b] + (int64_t)m.blocks[b].dn * P->ntile * P->nchunk_c;
+    c0[b + 1] = c0[b] + (int64_t)m.blocks[b].dn * P->ntile_c * P->nchunk_c;
   P->cols_items = c0.back();
   TRBL_REQUIRE(P->cols_items < (int64_t)1 << 31 && (P->cols_items + 7) * P->nthr_c < (int64_t)1 << 32,
                TRBL_E_INVALID, "problem too large for one launch");
   P->citem0.upload(c0);
-  P->shm_c = ((size_t)m.max_dp * rs_of(C, elt) * elt + 15) / 16 * 16;
+  P->shm_c = ((size_t)m.max_dp * rs_of(Cc, elt) * elt + 15) / 16 * 16;
   m.hv_plans[key] = std::move(owned);
   return *P;
 }

@@ -205,8 +205,9 @@ __device__ __forceinline__ GroupIt group_at(const HVArgs<T>& a, int b, int g, in
 }
 
 constexpr int MAXE = 8;           // neutron jumps per (target, class) kept in registers
-// A bin with MP > 1 targets per lane holds sectors wider than (MP / 2) * 1024 in its 72 KB row
-// buffer, so its tile rows (C * sizeof(T), a power of two) are at most 128 / MP bytes.
+// MP targets per lane multiply the accumulators: MP > 1 is used for tile rows (C * sizeof(T), a
+// power of two) of at most 128 / MP bytes, which is also all that a 72 KB buffer holds for
+// sectors wider than (MP / 2) * 1024.
 constexpr bool rows_mp_fits(size_t tile_row_bytes, int mp) { return tile_row_bytes * mp <= 128; }
 // LDS rows of the class table used by the target's proton jumps (smaller with the 36 KB row
 // buffers, so that two workgroups fit in the 160 KB of LDS of a CU)
@@ -218,15 +219,16 @@ constexpr int hs_bytes(int rbkb) { return rbkb == 36 ? 4096 : 8192; }
 // table rows of the proton ops sit in LDS; source rows stream through B0/B1.
 // SB (one row buffer): the current source row is staged and waited for at every step; used
 // for narrow sectors with wide source rows, where half the LDS lets two workgroups share a
-// CU and overlap each other's staging instead of their own.
+// CU and overlap each other's staging instead of their own, and for the 144 KB buffer of the
+// widest rows, where a wider column tile is worth more than the overlap.
 // MP (targets per lane): sectors wider than 1024 give each lane MP targets n', n' + 1024, ...,
 // so that a staged source row serves the whole sector instead of one 1024-wide chunk of it.
 template <class T, int C, int NTB, int RBKB, bool DMA, bool SB = false, int MP = 1>
 __global__ __launch_bounds__(NTB, (NTB == 768 && sizeof(T) == 4 && RBKB <= 36) ? 6 : 1) void hv_rows_kernel(HVArgs<T> a) {
   constexpr int MAXP = MP;  // targets per lane (sectors wider than MP * 1024 are split into chunks)
-  // neutron jumps per (target, class) in registers: fewer with 4 targets per lane (the rest are
-  // read from the table as they are used)
-  constexpr int NE = MP >= 4 ? 4 : MAXE;
+  // neutron jumps per (target, class) in registers: fewer with 4 targets per lane, fewest with
+  // 32-byte tile rows (the rest are read from the table as they are used)
+  constexpr int NE = MP >= 4 ? (C * (int)sizeof(T) >= 32 ? 2 : 4) : MAXE;
   constexpr int RBYTES = RBKB * 1024;
   constexpr int HSN = hs_bytes(RBKB) / (int)sizeof(T);
   __shared__ __align__(16) char B0[RBYTES];
@@ -354,10 +356,10 @@ __global__ __launch_bounds__(NTB, (NTB == 768 && sizeof(T) == 4 && RBKB <= 36) ?
 #pragma unroll
           for (int i = 0; i < NE; i++)
             if (i >= nm && i < ec[q]) gather<T, C>(acc[q], cf(er[q][i]), rd, er[q][i].x, rot);
-          // jumps beyond the register-held ones; with narrow tiles (wide sectors, where most jumps
-          // land here) four table loads are put in flight before their gathers
+          // jumps beyond the register-held ones; with 16-byte tile rows (wide sectors, where most
+          // jumps land here) four table loads are put in flight before their gathers
           int i = NE;
-          if constexpr (C * sizeof(T) <= 32)
+          if constexpr (C * sizeof(T) <= 16)
             for (; i + 4 <= ec[q]; i += 4) {
               int2 e[4];
 #pragma unroll
@@ -472,7 +474,7 @@ __global__ __launch_bounds__(1024) void hv_cols_kernel(HVArgs<T> a) {
 template <class T, int C, int NTB, int RB, int MP = 1>
 static void launch_rows(const HVArgs<T>& a, const HVBin& B, hipStream_t s) {
   const dim3 grid((unsigned)((B.items + 7) / 8 * 8)), block(B.nthr);
-  constexpr bool SB = NTB == 256;  // narrow sectors: one buffer, two or more workgroups per CU
+  constexpr bool SB = NTB == 256 || RB == 144;  // one buffer: narrow sectors, or the widest rows
   if (a.dma) hipLaunchKernelGGL((hv_rows_kernel<T, C, NTB, RB, true, SB, MP>), grid, block, 0, s, a);
   else hipLaunchKernelGGL((hv_rows_kernel<T, C, NTB, RB, false, SB, MP>), grid, block, 0, s, a);
 }
@@ -480,6 +482,13 @@ template <class T, int C, int MP>
 static void launch_cols(const HVArgs<T>& a, const HVPlan& P, hipStream_t s) {
   hipLaunchKernelGGL((hv_cols_kernel<T, C, MP>), dim3((unsigned)((P.cols_items + 7) / 8 * 8)), dim3(P.nthr_c),
                      P.shm_c, s, a);
+}
+
+template <class T, int CC>
+static void dispatch_cols(HVArgs<T>& a, const HVPlan& P, hipStream_t s) {
+  if (P.maxp_c == 1) launch_cols<T, CC, 1>(a, P, s);
+  else if (P.maxp_c == 2) launch_cols<T, CC, 2>(a, P, s);
+  else launch_cols<T, CC, 4>(a, P, s);
 }
 
 template <class T, int C>
@@ -491,23 +500,34 @@ static void dispatch_c(HVArgs<T>& a, const HVPlan& P, hipStream_t s) {
     a.bin_item0 = B.item0.as<int64_t>();
     a.bin_nblk = B.nblk;
 #define TRBL_ROWS_RB(NTB)                                                   \
-  (B.rb_kb == 24 ? launch_rows<T, C, NTB, 24>(a, B, s)                      \
-                 : B.rb_kb == 36 ? launch_rows<T, C, NTB, 36>(a, B, s) : launch_rows<T, C, NTB, 72>(a, B, s))
+  (B.rb_kb == 24   ? launch_rows<T, C, NTB, 24>(a, B, s)                    \
+   : B.rb_kb == 36 ? launch_rows<T, C, NTB, 36>(a, B, s)                    \
+   : B.rb_kb == 72 ? launch_rows<T, C, NTB, 72>(a, B, s)                    \
+                   : launch_rows<T, C, NTB, 144>(a, B, s))
     if (B.ntb == 256) TRBL_ROWS_RB(256);
     else if (B.ntb == 768) TRBL_ROWS_RB(768);
     else if (B.mp == 4) {
-      if constexpr (rows_mp_fits(C * sizeof(T), 4)) launch_rows<T, C, 1024, 72, 4>(a, B, s);
-      else TRBL_REQUIRE(false, TRBL_E_INVALID, "targets-per-lane plan does not match the column tile");
+      if constexpr (rows_mp_fits(C * sizeof(T), 4)) {
+        if (B.rb_kb == 144) launch_rows<T, C, 1024, 144, 4>(a, B, s);
+        else launch_rows<T, C, 1024, 72, 4>(a, B, s);
+      } else TRBL_REQUIRE(false, TRBL_E_INVALID, "targets-per-lane plan does not match the column tile");
     } else if (B.mp == 2) {
-      if constexpr (rows_mp_fits(C * sizeof(T), 2)) launch_rows<T, C, 1024, 72, 2>(a, B, s);
-      else TRBL_REQUIRE(false, TRBL_E_INVALID, "targets-per-lane plan does not match the column tile");
+      if constexpr (rows_mp_fits(C * sizeof(T), 2)) {
+        if (B.rb_kb == 144) launch_rows<T, C, 1024, 144, 2>(a, B, s);
+        else launch_rows<T, C, 1024, 72, 2>(a, B, s);
+      } else TRBL_REQUIRE(false, TRBL_E_INVALID, "targets-per-lane plan does not match the column tile");
     } else TRBL_ROWS_RB(1024);
 #undef TRBL_ROWS_RB
   }
   a.nchunk = P.nchunk_c;
-  if (P.maxp_c == 1) launch_cols<T, C, 1>(a, P, s);
-  else if (P.maxp_c == 2) launch_cols<T, C, 2>(a, P, s);
-  else launch_cols<T, C, 4>(a, P, s);
+  a.ntile = P.ntile_c;
+  if (P.Cc == C) dispatch_cols<T, C>(a, P, s);
+  else if (P.Cc * 2 == C) {
+    if constexpr (C / 2 >= 16 / (int)sizeof(T)) dispatch_cols<T, C / 2>(a, P, s);
+  } else {
+    if constexpr (C / 4 >= 16 / (int)sizeof(T)) dispatch_cols<T, C / 4>(a, P, s);
+  }
+  a.ntile = P.ntile;
 }
 
 // All launches of one block H.V (rows kernel per bin, then the columns kernel).

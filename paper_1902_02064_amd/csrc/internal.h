@@ -137,6 +137,7 @@ struct HVBin {
 };
 struct HVPlan {
   int C = 1, ntile = 1, nchunk_c = 1, maxp_c = 1, nthr_c = 64;
+  int Cc = 1, ntile_c = 1;  // columns kernel tile (narrower where the proton columns need it)
   int64_t cols_items = 0;
   size_t shm_c = 0;
   DevBuf citem0;

@@ -90,14 +90,15 @@ def test_apply_full_size_sampled_rows(wname, nrows):
 
 
 def test_apply_pf66_sampled_rows():
-    """pf shell 6+6 (D = 109,954,620; neutron sectors up to 3,952 SDs, so the rows kernel splits
-    targets into chunks and the column tile shrinks to fit LDS): 60 sampled rows against the oracle,
-    nb = 4 to keep the host-side input at 3.5 GB."""
+    """pf shell 6+6 (D = 109,954,620; neutron sectors up to 3,952 SDs, so the widest source rows go
+    through the 144 KB single row buffer, 4 targets per lane, and the columns kernel takes a
+    narrower tile): 60 sampled rows against the oracle. nb = 8 (FP64 tile of 4 columns, FP32 of
+    8), host-side input 7 GB."""
     w = WORKLOADS["pf66"]
-    say("case pf66 full size, nb=4")
+    say("case pf66 full size, nb=8")
     g, o = pair(w.orbits, w.n_prot, w.n_neut, w.twoM, w.tbme(), w.spe, w.spe)
     assert g.dim == o.dim == 109954620
-    V = random_block(2000, g.dim, 4)
+    V = random_block(2000, g.dim, 8)
     rng = np.random.default_rng(5)
     idx = np.unique(np.concatenate([rng.choice(g.dim, 60, replace=False), [0, g.dim - 1]]))
     ref = o.apply_rows(V, idx)
