@@ -40,13 +40,18 @@ static HVPlan& plan_for(const Model& m, int nb, size_t elt) {
   // TRBL_HV_XL=0: tiles sized for the 72 KB double buffer only, for comparison
   static const size_t row_cap =
       std::getenv("TRBL_HV_XL") && std::atoi(std::getenv("TRBL_HV_XL")) == 0 ? ROW_LARGE : ROW_XL;
-  while (C > cmin && (size_t)m.max_dn * C * elt > row_cap) C >>= 1;
-  TRBL_REQUIRE((size_t)m.max_dn * C * elt <= row_cap, TRBL_E_INVALID, "neutron sector too large for the LDS row tile");
+  // a row buffer holds the widest source row plus the zero row of the rows kernel
+  while (C > cmin && (size_t)(m.max_dn + 1) * C * elt > row_cap) C >>= 1;
+  TRBL_REQUIRE((size_t)(m.max_dn + 1) * C * elt <= row_cap, TRBL_E_INVALID, "neutron sector too large for the LDS row tile");
   // the columns kernel stages whole proton columns: its own, possibly narrower, tile
   int Cc = C;
   while (Cc > cmin && (size_t)m.max_dp * rs_of(Cc, elt) * elt > 144 * 1024) Cc >>= 1;
   TRBL_REQUIRE((size_t)m.max_dp * rs_of(Cc, elt) * elt <= 144 * 1024 && Cc * 4 >= C, TRBL_E_INVALID,
                "proton sector too large for the LDS column tile");
+  // one row of the pn coefficient table must fit the rows kernel's 8 KB coefficient area, and the
+  // double-buffered rows kernel holds every neutron jump of a class in registers
+  TRBL_REQUIRE(m.max_nj_class <= 32, TRBL_E_INVALID, "more than 32 neutron jumps of one class from one SD");
+  TRBL_REQUIRE((size_t)m.max_hncol * elt <= 8192, TRBL_E_INVALID, "pn operator class too large for the LDS table");
   P->C = C;
   P->ntile = (nb + C - 1) / C;
   P->Cc = Cc;
@@ -65,7 +70,7 @@ static HVPlan& plan_for(const Model& m, int nb, size_t elt) {
     }
     const int nthr = std::min(1024, (dn + 63) / 64 * 64);
     const int ntb = nthr <= 256 ? 256 : nthr <= 768 ? 768 : 1024;
-    const size_t need = (size_t)widest * C * elt;
+    const size_t need = (size_t)(widest + 1) * C * elt;
     const int rb = need <= ROW_SMALL ? 24 : need <= ROW_MID ? 36 : need <= ROW_LARGE ? 72 : 144;
     members[{ntb, rb}].push_back((int)b);
   }
@@ -87,6 +92,8 @@ static HVPlan& plan_for(const Model& m, int nb, size_t elt) {
       const int want = (maxdn > 2048 && mp_cap >= 4) ? 4 : 2;
       if (rows_mp_fits((size_t)C * elt, want)) B.mp = want;
     }
+    // register-held neutron jumps per class: every one of them with one target per lane
+    B.nr = B.mp > 1 ? 8 : (m.max_nj_class > 16 ? 32 : 16);
     B.nchunk = (maxdn + B.nthr * B.mp - 1) / (B.nthr * B.mp);
     std::vector<int64_t> i0(1, 0);
     for (int b : kv.second) i0.push_back(i0.back() + (int64_t)m.blocks[b].dp * P->ntile * B.nchunk);
@@ -125,7 +132,7 @@ static HVArgs<T> make_args(const Model& m, int nb, const void* V, int64_t ldv, v
   a.nblocks = (int)m.blocks.size();
   a.ncl = m.cl.nclass;
   a.tjmax = m.cl.tjmax;
-  a.nnum = m.n_neut <= MAXE ? m.n_neut : 0;
+  a.nnum = m.n_neut <= 8 ? m.n_neut : 0;  // number operators merged only while they are register-held
   a.nn_total = m.nn_total;
   // DMA staging needs 16-byte aligned chunks and full column tiles (set again once C is known)
   a.dma = ((uintptr_t)V % 16 == 0) && ((size_t)ldv * sizeof(T)) % 16 == 0;
@@ -142,7 +149,9 @@ static HVArgs<T> make_args(const Model& m, int nb, const void* V, int64_t ldv, v
   a.pg_start = d.pg_start.as<int>();
   a.pg_desc = d.pg_desc.as<int>();
   a.nj_start = d.nj_start.as<int>();
-  a.nj_pack = d.nj_pack.as<int2>();
+  a.nj32 = d.nj32.as<uint32_t>();
+  a.pg_cend = d.pg_cend.as<int>();
+  a.nlane = d.nlane.as<int>();
   a.h_off = d.h_off.as<int>();
   a.h_ncol = d.h_ncol.as<int>();
   a.pe_off = d.pe_off.as<int>();

@@ -24,6 +24,8 @@
 // banks at each step. Accumulator slot t of lane l therefore holds column chunk
 // (t + l) mod chunks-per-row, which the final store undoes.
 #pragma once
+#include <type_traits>
+
 #include "internal.h"
 
 namespace trbl {
@@ -50,7 +52,9 @@ struct HVArgs {
   const int* pg_start;  // per proton SD: first jump group
   const int* pg_desc;   // jump groups, 4 ints each: class, first jump, end jump, source row
   const int* nj_start;  // class-major: [cls * (nn_total + 1) + g]
-  const int2* nj_pack;  // (source local index, op << 1 | sign)
+  const uint32_t* nj32;  // the same jumps packed: sign << 31 | op << 16 | source local index
+  const int* pg_cend;    // per jump group: first group after the run of its class
+  const int* nlane;      // lane order of the rows kernel: sector-local neutron SD of each lane
   const int* h_off;
   const int* h_ncol;
   const T* h;
@@ -120,24 +124,30 @@ struct Tile {
   static constexpr int RB = C * (int)sizeof(T);    // bytes per row
   static_assert(CPR >= 1 && (CPR & (CPR - 1)) == 0, "tile width must be a power-of-two number of chunks");
   __device__ static __forceinline__ int at(int r, int k) { return r * RB + (k << 4); }
-  __device__ static __forceinline__ int rot() { return (int)threadIdx.x & (CPR - 1); }  // first chunk of this lane
+  __device__ static __forceinline__ int rot() { return (int)threadIdx.x & (CPR - 1); }  // chunk order of this lane
 };
 
-// Asynchronous copy of nrows rows (C values each, row stride ld) into the tile. Each lane
-// moves one 16-byte chunk per instruction; the chunks of one wavefront land contiguously.
+// Asynchronous copy of nrows rows (C values each, row stride ld) into the tile by the
+// global->LDS DMA of buffer loads: each lane moves one 16-byte chunk per instruction and the
+// chunks of one wavefront land contiguously. The row base is a buffer descriptor, the
+// wavefront's position a scalar offset and the lane's position a register that never changes,
+// so nothing the DMA reads is overwritten while it is in flight (out-of-range offsets read 0).
 template <class T, int C>
 __device__ __forceinline__ void stage_dma(char* lds, const T* src, int64_t ld, int nrows) {
+#if defined(__HIP_DEVICE_COMPILE__)  // buffer descriptors exist only in the device pass
   using L = Tile<T, C>;
   const int total = nrows * L::CPR;
   const int lane = threadIdx.x & 63;
-  for (int s0 = threadIdx.x & ~63; s0 < total; s0 += blockDim.x) {
-    const int s = s0 + lane;
-    if (s < total) {
-      const int r = s / L::CPR, k = s % L::CPR;
-      __builtin_amdgcn_global_load_lds((const void*)(src + (int64_t)r * ld + k * L::VPC),
-                                       (__attribute__((address_space(3))) void*)(lds + (s0 << 4)), 16, 0, 0);
-    }
-  }
+  const int rowb = (int)(ld * (int64_t)sizeof(T));
+  const int voff = (lane / L::CPR) * rowb + (lane % L::CPR) * 16;
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)src, (short)0, 0x7fffffff, 0x00020000);
+  const int w0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x & ~63);
+  const int wstep = __builtin_amdgcn_readfirstlane((int)blockDim.x);
+  for (int s0 = w0; s0 < total; s0 += wstep)
+    if (s0 + lane < total)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(lds + (s0 << 4)), 16, voff,
+                                               (s0 / L::CPR) * rowb, 0, 0);
+#endif
 }
 
 // Synchronous copy into the same layout (partial or unaligned column tiles), zero beyond cvalid.
@@ -152,28 +162,6 @@ __device__ __forceinline__ void stage_sync(char* lds, const T* src, int64_t ld, 
     for (int v = 0; v < L::VPC; v++) {
       const int c = k * L::VPC + v;
       d[v] = c < cvalid ? src[(int64_t)r * ld + c] : T(0);
-    }
-  }
-}
-
-// acc += coef * row r of the tile, accumulator slot t <- chunk (t + rot) mod CPR
-template <class T, int C>
-__device__ __forceinline__ void gather(T (&acc)[C], T coef, const char* lds, int r, int rot) {
-  using L = Tile<T, C>;
-  const char* row = lds + r * L::RB;
-#pragma unroll
-  for (int k = 0; k < L::CPR; k++) {
-    const char* p = row + (((k + rot) & (L::CPR - 1)) << 4);
-    if constexpr (sizeof(T) == 8) {
-      const double2 v = *reinterpret_cast<const double2*>(p);
-      acc[2 * k] += coef * v.x;
-      acc[2 * k + 1] += coef * v.y;
-    } else {
-      const float4 v = *reinterpret_cast<const float4*>(p);
-      acc[4 * k] += coef * v.x;
-      acc[4 * k + 1] += coef * v.y;
-      acc[4 * k + 2] += coef * v.z;
-      acc[4 * k + 3] += coef * v.w;
     }
   }
 }
@@ -204,33 +192,92 @@ __device__ __forceinline__ GroupIt group_at(const HVArgs<T>& a, int b, int g, in
   return {gend, a.ncl, 0, 0, -1, 0};
 }
 
-constexpr int MAXE = 8;           // neutron jumps per (target, class) kept in registers
+// Neutron jumps as the rows kernel reads them: one word per jump, sign in bit 31, operator
+// index inside its class in bits 16..30, source index inside its sector in bits 0..15.
+constexpr uint32_t NJ_SIGN = 0x80000000u;
+__device__ __forceinline__ int nj_src(uint32_t e) { return (int)(e & 0xFFFFu); }
+__device__ __forceinline__ int nj_op(uint32_t e) { return (int)((e >> 16) & 0x7FFFu); }
+// h with the jump's sign applied by flipping the sign bit
+__device__ __forceinline__ double signed_coef(double h, uint32_t e) {
+  return __hiloint2double(__double2hiint(h) ^ (int)(e & NJ_SIGN), __double2loint(h));
+}
+__device__ __forceinline__ float signed_coef(float h, uint32_t e) {
+  return __int_as_float(__float_as_int(h) ^ (int)(e & NJ_SIGN));
+}
+
 // MP targets per lane multiply the accumulators: MP > 1 is used for tile rows (C * sizeof(T), a
 // power of two) of at most 128 / MP bytes, which is also all that a 72 KB buffer holds for
 // sectors wider than (MP / 2) * 1024.
 constexpr bool rows_mp_fits(size_t tile_row_bytes, int mp) { return tile_row_bytes * mp <= 128; }
-// LDS rows of the class table used by the target's proton jumps (smaller with the 36 KB row
-// buffers, so that two workgroups fit in the 160 KB of LDS of a CU)
-constexpr int hs_bytes(int rbkb) { return rbkb == 36 ? 4096 : 8192; }
+// LDS bytes of the coefficient rows next to the row buffers: 16 KB where the buffers take 144 KB
+// (one workgroup per CU), else 8 KB (so that two workgroups of 72 KB buffers share a CU)
+constexpr int hs_bytes(int rbkb, bool sb) { return (sb ? rbkb : 2 * rbkb) >= 144 ? 16384 : 8192; }
+
+// acc += coef * row of the tile at `row`: the CPR chunk loads are issued together, then the FMAs.
+// Accumulator slot t holds chunk t ^ rot (rot = lane mod CPR), so that the lanes of a wavefront
+// reading random rows start on different LDS banks; since rows are CPR * 16 bytes and aligned,
+// the address of chunk t ^ rot is (row + rot * 16) ^ (t * 16).
+template <class T>
+using RowChunk = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+template <class T, int C>
+__device__ __forceinline__ void load_row(RowChunk<T>* v, const char* lds, int row_byte) {
+  using L = Tile<T, C>;
+  const int a0 = row_byte + (L::rot() << 4);
+#pragma unroll
+  for (int t = 0; t < L::CPR; t++) v[t] = *reinterpret_cast<const RowChunk<T>*>(lds + (a0 ^ (t << 4)));
+}
+template <class T, int C>
+__device__ __forceinline__ void fma_row(T (&acc)[C], T coef, const RowChunk<T>* v) {
+  using L = Tile<T, C>;
+#pragma unroll
+  for (int t = 0; t < L::CPR; t++) {
+    if constexpr (sizeof(T) == 8) {
+      acc[2 * t] += coef * v[t].x;
+      acc[2 * t + 1] += coef * v[t].y;
+    } else {
+      acc[4 * t] += coef * v[t].x;
+      acc[4 * t + 1] += coef * v[t].y;
+      acc[4 * t + 2] += coef * v[t].z;
+      acc[4 * t + 3] += coef * v[t].w;
+    }
+  }
+}
+template <class T, int C>
+__device__ __forceinline__ void gather_row(T (&acc)[C], T coef, const char* lds, int row_byte) {
+  RowChunk<T> v[Tile<T, C>::CPR];
+  load_row<T, C>(v, lds, row_byte);
+  fma_row<T, C>(acc, coef, v);
+}
 
 // Rows kernel: neutron-neutron and proton-neutron parts of W for one proton row p' of one
-// block (App. B). One lane owns target n' (or MP of them; wider sectors are split in chunks) and the C
-// columns of the tile. Its neutron jumps of the current class sit in registers; the class
-// table rows of the proton ops sit in LDS; source rows stream through B0/B1.
+// block (App. B). One lane owns one target n' (or MP of them: lanes l, l + width, ...) and the
+// C columns of the tile; lane l of a sector serves the SD nlane[sector start + l], an order in
+// which neighbouring lanes have similar numbers of jumps per class.
+//
+// The proton jumps of p' are walked as groups (one source row p each, several jumps only for
+// the proton number operators), class by class. Per class, each lane holds its neutron jumps
+// of the opposite class in registers, and LDS holds one coefficient row per group: the proton
+// signs and the jumps of a group summed into HS[group][op_n] = sum_j s_j h[op_p(j)][op_n].
+// A step (one group, one source row) then costs, per element, one LDS read of the coefficient
+// and CPR 16-byte LDS reads of the source row, and nothing else: the compute phase issues no
+// global or scalar loads, so the asynchronous copy of the next source row (global->LDS DMA
+// into the other buffer) stays in flight until the closing barrier.
+//
+// With one target per lane every lane runs as many elements as the longest jump list of its
+// wavefront; shorter lists are padded with a jump to row Z of the buffer, a row of zeros that
+// no copy overwrites, so the element loop has no divergent branches (and, with the lane order
+// above, little padding). In the class of no change of M and
+// parity each neutron SD's number operators (source n' itself) are summed into one element.
 // SB (one row buffer): the current source row is staged and waited for at every step; used
-// for narrow sectors with wide source rows, where half the LDS lets two workgroups share a
-// CU and overlap each other's staging instead of their own, and for the 144 KB buffer of the
-// widest rows, where a wider column tile is worth more than the overlap.
-// MP (targets per lane): sectors wider than 1024 give each lane MP targets n', n' + 1024, ...,
-// so that a staged source row serves the whole sector instead of one 1024-wide chunk of it.
-template <class T, int C, int NTB, int RBKB, bool DMA, bool SB = false, int MP = 1>
-__global__ __launch_bounds__(NTB, (NTB == 768 && sizeof(T) == 4 && RBKB <= 36) ? 6 : 1) void hv_rows_kernel(HVArgs<T> a) {
-  constexpr int MAXP = MP;  // targets per lane (sectors wider than MP * 1024 are split into chunks)
-  // neutron jumps per (target, class) in registers: fewer with 4 targets per lane, fewest with
-  // 32-byte tile rows (the rest are read from the table as they are used)
-  constexpr int NE = MP >= 4 ? (C * (int)sizeof(T) >= 32 ? 2 : 4) : MAXE;
+// for narrow sectors, where half the LDS lets two workgroups share a CU and overlap each
+// other's staging, and for the 144 KB buffer of the widest rows.
+template <class T, int C, int NTB, int RBKB, bool DMA, bool SB = false, int MP = 1, int NR = 16>
+__global__ __launch_bounds__(NTB) void hv_rows_kernel(HVArgs<T> a) {
+  using L = Tile<T, C>;
   constexpr int RBYTES = RBKB * 1024;
-  constexpr int HSN = hs_bytes(RBKB) / (int)sizeof(T);
+  constexpr int HSN = hs_bytes(RBKB, SB) / (int)sizeof(T);
+  constexpr int ZROW = RBYTES / L::RB - 1;  // the zero row of each buffer
+  static_assert(ZROW < 65536, "row index must fit the packed jumps");
   __shared__ __align__(16) char B0[RBYTES];
   __shared__ __align__(16) char B1[SB ? 16 : RBYTES];
   __shared__ __align__(16) T HS[HSN];
@@ -250,14 +297,19 @@ __global__ __launch_bounds__(NTB, (NTB == 768 && sizeof(T) == 4 && RBKB <= 36) ?
   const int64_t off = a.blk_off[b];
   const int gp = a.blk_p0[b] + pl;
   const int gn0 = a.blk_n0[b];
-  const int tlo = tc * nthr * MAXP;
+  const int tlo = tc * nthr * MP;
   if (tlo >= dn) return;  // chunk beyond this block's sector (bins mix sector widths)
-  const int thi = min(dn, tlo + nthr * MAXP);
+  const int thi = min(dn, tlo + nthr * MP);
   const int ncl = a.ncl;
-  const int rot = Tile<T, C>::rot();
-  T acc[MAXP][C];
+  int tg[MP];  // this lane's targets (sector-local neutron index), -1 for none
 #pragma unroll
-  for (int q = 0; q < MAXP; q++)
+  for (int q = 0; q < MP; q++) {
+    const int ln = tlo + q * nthr + tid;
+    tg[q] = ln < thi ? a.nlane[gn0 + ln] : -1;
+  }
+  T acc[MP][C];
+#pragma unroll
+  for (int q = 0; q < MP; q++)
 #pragma unroll
     for (int c = 0; c < C; c++) acc[q][c] = T(0);
 
@@ -271,60 +323,129 @@ __global__ __launch_bounds__(NTB, (NTB == 768 && sizeof(T) == 4 && RBKB <= 36) ?
   GroupIt it = group_at(a, b, ldu(a.pg_start, gp), gend);
   stage_row(B0, off + (int64_t)pl * dn, dn);
   if (!SB && it.cls < ncl) stage_row(B1, a.blk_off[it.sb] + (int64_t)it.p * a.blk_dn[it.sb], a.blk_dn[it.sb]);
+  for (int k = tid; k < L::CPR; k += nthr) {  // the zero rows (above every staged row)
+    *reinterpret_cast<float4*>(B0 + ZROW * L::RB + (k << 4)) = make_float4(0.f, 0.f, 0.f, 0.f);
+    if constexpr (!SB) *reinterpret_cast<float4*>(B1 + ZROW * L::RB + (k << 4)) = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 
-  // own row: neutron-neutron part (single-particle energies included)
+  // own row: neutron-neutron part (single-particle energies included), sliced ELL entries read
+  // four at a time
   const int ns0l = a.blk_nslice0[b];
 #pragma unroll
-  for (int q = 0; q < MAXP; q++) {
-    const int n = tlo + q * nthr + tid;
-    if (n < thi) {
-      const int sl = ns0l + n / 64, ln = n % 64;
+  for (int q = 0; q < MP; q++) {
+    const int ln = tlo + q * nthr + tid;
+    if (ln < thi) {
+      const int sl = ns0l + ln / 64, lo = ln % 64;
       const int base = a.ne_off[sl], wd = a.ne_w[sl];
-      for (int k = 0; k < wd; k++) {
-        const int at = base + k * 64 + ln;
-        gather<T, C>(acc[q], a.ne_val[at], B0, a.ne_col[at], rot);
+      for (int k = 0; k < wd; k += 4) {
+        int cc[4];
+        T vv[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          const int at = base + (k + u) * 64 + lo;
+          cc[u] = k + u < wd ? a.ne_col[at] : 0;
+          vv[u] = k + u < wd ? a.ne_val[at] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) gather_row<T, C>(acc[q], vv[u], B0, cc[u] * L::RB);
       }
     }
   }
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 
   // proton-neutron part
-  int2 er[MAXP][NE];
-  int eb[MAXP], ec[MAXP];
-  int cur = -1, j0c = 0, hn = 0;
-  bool hs_lds = false;
-  const T* hg = a.h;
-  auto step = [&](const char* rd, char* wr) __attribute__((always_inline)) {
-    if (it.cls != cur) {  // new class: neutron jumps to registers, class-table rows to LDS
-      cur = it.cls;
-      const int cn = (2 * a.tjmax - cur / 2) * 2 + (cur & 1);
-      const int* ns0 = a.nj_start + (int64_t)cn * (a.nn_total + 1) + gn0;
+  const uint32_t zj = (uint32_t)ZROW;  // padding jump: operator 0, row Z
+  const int dcls = 2 * a.tjmax;        // class of no change of M and parity
+  uint32_t er[MP][NR];
+  int eb[MP], ec[MP];
+  uint32_t e0[MP];  // first element: a jump, or (number-operator class) the own row
+  uint32_t nmo[MP][4];  // number-operator columns of the coefficient rows, two 16-bit fields a word
+  int nm = 0, ecm = 0;
+  int cur = -1, hs_g0 = 0, hs_gn = 0, hn = 1;
+  // class change: this lane's neutron jumps of the opposite class into registers
+  auto load_class = [&](int cls) __attribute__((always_inline)) {
+    cur = cls;
+    nm = (cls == dcls) ? a.nnum : 0;
+    const int cn = (2 * a.tjmax - cls / 2) * 2 + (cls & 1);
+    const int* ns0 = a.nj_start + (int64_t)cn * (a.nn_total + 1) + gn0;
+    int emax = 0;
 #pragma unroll
-      for (int q = 0; q < MAXP; q++) {
-        const int n = tlo + q * nthr + tid;
-        eb[q] = n < thi ? ns0[n] : 0;
-        ec[q] = n < thi ? ns0[n + 1] - eb[q] : 0;
+    for (int q = 0; q < MP; q++) {
+      // loads are unconditional (every index is valid: lanes without a target read entry 0,
+      // and the table is padded by 32 entries) and pinned here, before the DMA of the step:
+      // a load left for the compiler to sink into the compute phase would make it wait there
+      const int n = tg[q];
+      const int ja = ns0[max(n, 0)], jb = ns0[max(n, 0) + 1];
+      const int j0 = n >= 0 ? ja : 0;
+      const int cnt = n >= 0 ? jb - ja : 0;
+      if constexpr (MP == 1) {
+        // element 0: the merged number operators (row n'), else the first jump; the rest after it
+        const int skip = nm > 0 ? nm : 1;
+        uint32_t f[8];
 #pragma unroll
-        for (int i = 0; i < NE; i++) {
-          er[q][i] = make_int2(0, 0);
-          if (i < ec[q]) er[q][i] = a.nj_pack[eb[q] + i];
-          // pin the loads here (before the barrier and the next DMA), not next to their first use
-          asm volatile("" ::"v"(er[q][i].x), "v"(er[q][i].y));
+        for (int k = 0; k < 8; k++) f[k] = a.nj32[j0 + k];
+        e0[q] = n < 0 ? zj : nm > 0 ? (uint32_t)n : (cnt > 0 ? f[0] : zj);
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+          nmo[q][k] = n >= 0 ? (uint32_t)nj_op(f[2 * k]) | ((uint32_t)nj_op(f[2 * k + 1]) << 16) : 0u;
+        eb[q] = j0 + skip;
+        ec[q] = max(cnt - skip, 0);
+#pragma unroll
+        for (int i = 0; i < NR; i++) {
+          const uint32_t e = a.nj32[eb[q] + i];
+          er[q][i] = i < ec[q] ? e : zj;
         }
+        asm volatile("" ::"v"(e0[q]));
+#pragma unroll
+        for (int k = 0; k < 4; k++) asm volatile("" ::"v"(nmo[q][k]));
+      } else {
+        eb[q] = j0;
+        ec[q] = cnt;
+#pragma unroll
+        for (int i = 0; i < NR; i++) er[q][i] = a.nj32[eb[q] + i];
       }
-      j0c = ldu(a.pj_start, gp * ncl + cur);
-      const int nj = ldu(a.pj_start, gp * ncl + cur + 1) - j0c;
-      hn = ldu(a.h_ncol, cur);
-      hg = a.h + ldu(a.h_off, cur);
-      hs_lds = nj * hn <= HSN;
-      if (hs_lds)
-        for (int e = tid; e < nj * hn; e += nthr) {
-          const int jj = e / hn, o = e - jj * hn;
-          HS[e] = hg[(a.pj_meta[j0c + jj] >> 1) * hn + o];
-        }
-      __builtin_amdgcn_s_waitcnt(0);  // entries in registers before any DMA is in flight
+#pragma unroll
+      for (int i = 0; i < NR; i++) asm volatile("" ::"v"(er[q][i]));
+      emax = max(emax, ec[q]);
+    }
+    // longest list of the wavefront (uniform)
+    ecm = 0;
+#pragma unroll
+    for (int i = 0; i < NR; i++)
+      if (__builtin_amdgcn_ballot_w64(emax > i) != 0) ecm = i + 1;
+    hn = ldu(a.h_ncol, cls);
+  };
+  // coefficient rows of the groups g0 .. (end of the class run, or as many as HS holds)
+  auto load_hs = [&](int g0) __attribute__((always_inline)) {
+    const int cend = ldu(a.pg_cend, g0);
+    hs_g0 = g0;
+    hs_gn = min(cend - g0, HSN / hn);
+    const T* hg = a.h + ldu(a.h_off, cur);
+    for (int e = tid; e < hs_gn * hn; e += nthr) {
+      const int gl = e / hn, o = e - gl * hn;
+      const int* d = a.pg_desc + 4 * (int64_t)(g0 + gl);
+      T sum = T(0);
+      for (int j = d[1]; j < d[2]; j++) {
+        const int pm = a.pj_meta[j];
+        const T hv = hg[(pm >> 1) * hn + o];
+        sum += (pm & 1) ? -hv : hv;
+      }
+      HS[e] = sum;
+    }
+  };
+  auto step = [&](const char* rd, char* wr) __attribute__((always_inline)) {
+    if (it.cls != cur || it.g >= hs_g0 + hs_gn) {
+      if (it.cls != cur) {
+        load_class(it.cls);
+        // also here, so that no path the compiler makes around the barrier below carries these
+        // loads into the compute phase (a wait for them there would also wait for the DMA)
+        __builtin_amdgcn_s_waitcnt(0);
+      }
+      load_hs(it.g);
+      __builtin_amdgcn_s_waitcnt(0);  // jumps in registers, HS written, before any DMA is in flight
       __syncthreads();
     }
     const GroupIt nx = group_at(a, b, it.g + 1, gend);
@@ -335,67 +456,50 @@ __global__ __launch_bounds__(NTB, (NTB == 768 && sizeof(T) == 4 && RBKB <= 36) ?
     } else if (nx.cls < ncl) {
       stage_row(wr, ldu(a.blk_off, nx.sb) + (int64_t)nx.p * ldu(a.blk_dn, nx.sb), ldu(a.blk_dn, nx.sb));
     }
-    // hr points into LDS or into global memory: two copies of the loop keep every load
-    // typed (a generic pointer would make the compiler wait for the DMA in flight).
-    // Terms with the same source element are summed before the row is read: in the class of
-    // zero change of M and parity (the diagonal class) every neutron SD's first nnum jumps are
-    // its number operators (source n' itself), and a group of several proton jumps (the
-    // number operators, source p') shares every neutron entry.
-    const int nm = cur == 2 * a.tjmax ? a.nnum : 0;
-    auto apply = [&](auto hrow) __attribute__((always_inline)) {
-      auto body = [&](auto cf) __attribute__((always_inline)) {
+    const T* hrow = HS + (it.g - hs_g0) * hn;
+    auto coef = [&](uint32_t e) __attribute__((always_inline)) { return signed_coef(hrow[nj_op(e)], e); };
+    auto rowb = [&](uint32_t e) __attribute__((always_inline)) { return nj_src(e) * L::RB; };
+    if constexpr (MP == 1) {
+      RowChunk<T> buf[1][L::CPR];
+      T cf[1];
+      // element 0
+      if (nm > 0) {
+        T sum = T(0);
 #pragma unroll
-        for (int q = 0; q < MAXP; q++) {
-          if (nm > 0 && ec[q] >= nm) {
-            T sum = T(0);
-#pragma unroll
-            for (int i = 0; i < NE; i++)
-              if (i < nm) sum += cf(er[q][i]);
-            gather<T, C>(acc[q], sum, rd, er[q][0].x, rot);
-          }
-#pragma unroll
-          for (int i = 0; i < NE; i++)
-            if (i >= nm && i < ec[q]) gather<T, C>(acc[q], cf(er[q][i]), rd, er[q][i].x, rot);
-          // jumps beyond the register-held ones; with 16-byte tile rows (wide sectors, where most
-          // jumps land here) four table loads are put in flight before their gathers
-          int i = NE;
-          if constexpr (C * sizeof(T) <= 16)
-            for (; i + 4 <= ec[q]; i += 4) {
-              int2 e[4];
-#pragma unroll
-              for (int u = 0; u < 4; u++) e[u] = a.nj_pack[eb[q] + i + u];
-#pragma unroll
-              for (int u = 0; u < 4; u++) gather<T, C>(acc[q], cf(e[u]), rd, e[u].x, rot);
-            }
-          for (; i < ec[q]; i++) {
-            const int2 e = a.nj_pack[eb[q] + i];
-            gather<T, C>(acc[q], cf(e), rd, e.x, rot);
-          }
-        }
-      };
-      if (it.je - it.jg == 1) {
-        const int pm = ldu(a.pj_meta, it.jg);
-        const auto hr = hrow(it.jg, pm);
-        body([&](int2 e) __attribute__((always_inline)) {
-          const T hv = hr[e.y >> 1];
-          return ((e.y ^ pm) & 1) ? -hv : hv;
-        });
+        for (int k = 0; k < 8; k++)
+          if (k < nm) sum += hrow[(nmo[0][k >> 1] >> (16 * (k & 1))) & 0xFFFFu];  // number operators carry no sign
+        cf[0] = sum;
+        load_row<T, C>(buf[0], rd, (int)(e0[0] & 0xFFFFu) * L::RB);
       } else {
-        body([&](int2 e) __attribute__((always_inline)) {
-          T sum = T(0);
-          for (int j = it.jg; j < it.je; j++) {
-            const int pm = ldu(a.pj_meta, j);
-            const T hv = hrow(j, pm)[e.y >> 1];
-            sum += ((e.y ^ pm) & 1) ? -hv : hv;
-          }
-          return sum;
-        });
+        cf[0] = coef(e0[0]);
+        load_row<T, C>(buf[0], rd, rowb(e0[0]));
       }
-    };
-    if (hs_lds)
-      apply([&](int j, int) __attribute__((always_inline)) { return HS + (j - j0c) * hn; });
-    else
-      apply([&](int, int pm) __attribute__((always_inline)) { return hg + (pm >> 1) * hn; });
+      fma_row<T, C>(acc[0], cf[0], buf[0]);
+      // elements 1 .. ecm (uniform trip count: padded lists, no divergent branches)
+#pragma unroll
+      for (int i = 0; i < NR; i++)
+        if (i < ecm) gather_row<T, C>(acc[0], coef(er[0][i]), rd, rowb(er[0][i]));
+    } else {
+#pragma unroll
+      for (int q = 0; q < MP; q++) {
+        if (tg[q] < 0) continue;
+        if (nm > 0) {
+          T sum = T(0);
+#pragma unroll
+          for (int i = 0; i < NR; i++)
+            if (i < nm) sum += coef(er[q][i]);
+          gather_row<T, C>(acc[q], sum, rd, rowb(er[q][0]));
+        }
+#pragma unroll
+        for (int i = 0; i < NR; i++)
+          if (i >= nm && i < ec[q]) gather_row<T, C>(acc[q], coef(er[q][i]), rd, rowb(er[q][i]));
+        // jumps beyond the register-held ones, read from the table
+        for (int i = NR; i < ec[q]; i++) {
+          const uint32_t e = a.nj32[eb[q] + i];
+          gather_row<T, C>(acc[q], coef(e), rd, rowb(e));
+        }
+      }
+    }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     it = nx;
@@ -409,15 +513,13 @@ __global__ __launch_bounds__(NTB, (NTB == 768 && sizeof(T) == 4 && RBKB <= 36) ?
       step(B0, B1);
     }
   }
-  using L = Tile<T, C>;
 #pragma unroll
-  for (int q = 0; q < MAXP; q++) {
-    const int n = tlo + q * nthr + tid;
-    if (n < thi) {
-      T* w = a.W + (off + (int64_t)pl * dn + n) * a.ldw + c0;
+  for (int q = 0; q < MP; q++) {
+    if (tg[q] >= 0) {
+      T* w = a.W + (off + (int64_t)pl * dn + tg[q]) * a.ldw + c0;
 #pragma unroll
       for (int t = 0; t < L::CPR; t++) {
-        const int k = (t + rot) & (L::CPR - 1);
+        const int k = t ^ L::rot();
 #pragma unroll
         for (int v = 0; v < L::VPC; v++)
           if (k * L::VPC + v < cvalid) w[k * L::VPC + v] = acc[q][t * L::VPC + v];
@@ -475,8 +577,20 @@ template <class T, int C, int NTB, int RB, int MP = 1>
 static void launch_rows(const HVArgs<T>& a, const HVBin& B, hipStream_t s) {
   const dim3 grid((unsigned)((B.items + 7) / 8 * 8)), block(B.nthr);
   constexpr bool SB = NTB == 256 || RB == 144;  // one buffer: narrow sectors, or the widest rows
-  if (a.dma) hipLaunchKernelGGL((hv_rows_kernel<T, C, NTB, RB, true, SB, MP>), grid, block, 0, s, a);
-  else hipLaunchKernelGGL((hv_rows_kernel<T, C, NTB, RB, false, SB, MP>), grid, block, 0, s, a);
+  // the copy variant is a template parameter: a kernel that can take either path makes the
+  // compiler wait for the DMA in flight before every LDS read
+  if constexpr (MP == 1) {
+    if (B.nr == 32) {
+      if (a.dma) hipLaunchKernelGGL((hv_rows_kernel<T, C, NTB, RB, true, SB, MP, 32>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((hv_rows_kernel<T, C, NTB, RB, false, SB, MP, 32>), grid, block, 0, s, a);
+    } else {
+      if (a.dma) hipLaunchKernelGGL((hv_rows_kernel<T, C, NTB, RB, true, SB, MP, 16>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((hv_rows_kernel<T, C, NTB, RB, false, SB, MP, 16>), grid, block, 0, s, a);
+    }
+  } else {
+    if (a.dma) hipLaunchKernelGGL((hv_rows_kernel<T, C, NTB, RB, true, SB, MP, 8>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((hv_rows_kernel<T, C, NTB, RB, false, SB, MP, 8>), grid, block, 0, s, a);
+  }
 }
 template <class T, int C, int MP>
 static void launch_cols(const HVArgs<T>& a, const HVPlan& P, hipStream_t s) {

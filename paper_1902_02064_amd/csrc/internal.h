@@ -112,6 +112,9 @@ struct DeviceTables {
   // jumps
   DevBuf pj_start, pj_idx, pj_meta, nj_start, nj_idx, nj_meta, pj_pack, nj_pack;  // nj_* class-major
   DevBuf pg_start, pg_desc;  // per proton SD: jump groups (class, first, end, source row) as int4
+  DevBuf pg_cend;            // per jump group: first group after the run of its class
+  DevBuf nj32;               // neutron jumps, class-major, packed: sign << 31 | op << 16 | source
+  DevBuf nlane;              // per neutron SD slot (sector start + lane): the SD's index in its sector
   DevBuf h_off, h_ncol, h64, h32;
   DevBuf pp_ptr, pp_col, pp_v64, pp_v32, nn_ptr, nn_col, nn_v64, nn_v32;
   DevBuf pe_off, pe_w, pe_col, pe_v64, pe_v32, ne_off, ne_w, ne_col, ne_v64, ne_v32;  // sliced ELL
@@ -132,6 +135,7 @@ struct DeviceTables {
 struct HVBin {
   int nthr = 64, ntb = 256, nchunk = 1, rb_kb = 24, nblk = 0;  // width, its launch bound, chunks, LDS row KB
   int mp = 1;                                                    // targets per lane (1024-wide, 72 KB bins)
+  int nr = 16;                                                   // neutron jumps per class held in registers
   int64_t items = 0;
   DevBuf blocks, item0;  // block ids of the bin, first work item of each (nblk + 1)
 };
@@ -173,6 +177,9 @@ struct Model {
   // sizes for kernels
   int64_t np_total = 0, nn_total = 0;
   int pj_count = 0, nj_count = 0;
+  int max_nj_class = 0;  // most neutron jumps of one SD in one class
+  int max_hs_class = 0;  // most coefficient-table entries of one proton SD's jump groups of one class
+  int max_hncol = 0;     // widest row of the pn coefficient table
   int max_dn = 0, max_dp = 0;
   std::vector<int> h_off_host, h_ncol_host;
   std::vector<int> src_blk_host;        // per (block, class): source block or -1

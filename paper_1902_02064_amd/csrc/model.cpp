@@ -447,9 +447,48 @@ void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const
       ptr.push_back((int)col.size());
     }
     std::vector<float> val32(val.begin(), val.end());
-    // sliced-ELL copy for the H.V kernels: slices of 64 consecutive SDs of one sector (one
-    // wavefront of targets), padded to the longest row of the slice, entry k of lane l at
-    // base + k * 64 + l so the 64 lanes of a wavefront read 64 consecutive entries.
+    // Lane order of the rows kernel inside each neutron sector: SDs sorted by their number of
+    // one-body jumps in each class (the class of no change first, then outwards), so that the
+    // 64 targets of a wavefront have similar jump counts and few lanes idle while the longest
+    // list of the wavefront is worked through. Protons keep the sector order.
+    std::vector<int> lane_sd(S.words.size());
+    for (size_t g = 0; g < S.words.size(); g++) lane_sd[g] = (int)(g - S.sectors[S.sector_of[g]].start);
+    if (s == 1) {
+      const int nc = m.cl.nclass;
+      std::vector<int> cnt(S.words.size() * (size_t)nc, 0);
+      for (size_t g = 0; g < S.words.size(); g++) {
+        const uint64_t w = S.words[g];
+        for (uint64_t xx = w; xx; xx &= xx - 1) {
+          const int x = __builtin_ctzll(xx);
+          const uint64_t r0 = w & ~(1ull << x);
+          for (int y = 0; y < ns; y++) {
+            if (r0 & (1ull << y)) continue;
+            if (S.index.find(r0 | (1ull << y)) == S.index.end()) continue;
+            const int flip = (m.orbits[m.st_orb[x]].l + m.orbits[m.st_orb[y]].l) & 1;
+            cnt[g * nc + m.cl.cls(m.st_tm[y] - m.st_tm[x], flip)]++;
+          }
+        }
+      }
+      std::vector<int> corder;  // classes by |change of 2M|, the unchanged class first
+      for (int di = 0; di <= m.cl.tjmax * 2; di += 2)  // changes of 2M are even
+        for (int f = 0; f < 2; f++)
+          for (int sg = (di == 0 ? 1 : -1); sg <= 1; sg += 2) corder.push_back(m.cl.cls(sg * di, f));
+      for (const auto& sec : S.sectors) {
+        int* o = lane_sd.data() + sec.start;
+        std::stable_sort(o, o + sec.size, [&](int a, int b) {
+          for (int c : corder) {
+            const int ca = cnt[(size_t)(sec.start + a) * nc + c], cb = cnt[(size_t)(sec.start + b) * nc + c];
+            if (ca != cb) return ca > cb;
+          }
+          return false;
+        });
+      }
+      m.dt.nlane.upload(lane_sd);
+    }
+    // sliced-ELL copy for the H.V kernels: slices of 64 consecutive lanes of one sector (one
+    // wavefront of targets, in the lane order above), padded to the longest row of the slice,
+    // entry k of lane l at base + k * 64 + l so the 64 lanes of a wavefront read 64 consecutive
+    // entries.
     {
       std::vector<int> soff, sw, sec_slice0, ecol;
       std::vector<double> eval;
@@ -457,19 +496,23 @@ void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const
         sec_slice0.push_back((int)sw.size());
         for (int r0 = 0; r0 < sec.size; r0 += 64) {
           int w = 0;
-          for (int r = r0; r < std::min(sec.size, r0 + 64); r++)
-            w = std::max(w, ptr[sec.start + r + 1] - ptr[sec.start + r]);
+          for (int r = r0; r < std::min(sec.size, r0 + 64); r++) {
+            const int g = sec.start + lane_sd[sec.start + r];
+            w = std::max(w, ptr[g + 1] - ptr[g]);
+          }
           soff.push_back((int)ecol.size());
           sw.push_back(w);
           const size_t base = ecol.size();
           ecol.resize(base + (size_t)w * 64, 0);
           eval.resize(base + (size_t)w * 64, 0.0);
-          for (int r = r0; r < std::min(sec.size, r0 + 64); r++)
-            for (int k = ptr[sec.start + r]; k < ptr[sec.start + r + 1]; k++) {
-              const size_t at = base + (size_t)(k - ptr[sec.start + r]) * 64 + (r - r0);
+          for (int r = r0; r < std::min(sec.size, r0 + 64); r++) {
+            const int g = sec.start + lane_sd[sec.start + r];
+            for (int k = ptr[g]; k < ptr[g + 1]; k++) {
+              const size_t at = base + (size_t)(k - ptr[g]) * 64 + (r - r0);
               ecol[at] = col[k];
               eval[at] = val[k];
             }
+          }
         }
       }
       std::vector<float> eval32(eval.begin(), eval.end());
@@ -537,6 +580,7 @@ void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const
   }
   m.h_off_host = hoff;
   m.h_ncol_host = hncol;
+  m.max_hncol = *std::max_element(hncol.begin(), hncol.end());
   std::vector<float> h32(h.begin(), h.end());
   m.dt.h_off.upload(hoff);
   m.dt.h_ncol.upload(hncol);
@@ -609,6 +653,22 @@ void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const
       pack[2 * q] = jidx[q];
       pack[2 * q + 1] = jmeta[q];
     }
+    if (s == 1) {
+      // neutron jumps packed in one word for the rows kernel: sign in bit 31, op index in
+      // bits 16..30, source index inside its sector in bits 0..15
+      std::vector<uint32_t> p32(jidx.size() + 32, 0u);  // padded: register loads read up to 32 past a list
+      for (size_t q = 0; q < jidx.size(); q++) {
+        const int op = jmeta[q] >> 1;
+        TRBL_REQUIRE(jidx[q] >= 0 && jidx[q] < 65536 && op < 32768, TRBL_E_INVALID,
+                     "neutron sector or operator class too large for the packed jump lists");
+        p32[q] = ((uint32_t)(jmeta[q] & 1) << 31) | ((uint32_t)op << 16) | (uint32_t)jidx[q];
+      }
+      m.dt.nj32.upload(p32);
+      int mx = 0;
+      for (int c = 0; c < ncl; c++)
+        for (int64_t g = 0; g < nsd; g++) mx = std::max(mx, start[c * (nsd + 1) + g + 1] - start[c * (nsd + 1) + g]);
+      m.max_nj_class = mx;
+    }
     (s == 0 ? m.dt.pj_start : m.dt.nj_start).upload(start);
     if (s == 0) {
       // proton jump groups of every SD: runs of jumps of one class with one source row,
@@ -625,8 +685,18 @@ void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const
           }
       }
       gstart[nsd] = (int)(gdesc.size() / 4);
+      // per group: the first group after the run of its class (same SD)
+      const int ng = (int)(gdesc.size() / 4);
+      std::vector<int> cend(ng + 1, ng);
+      for (int64_t g = 0; g < nsd; g++)
+        for (int q = gstart[g + 1] - 1; q >= gstart[g]; q--)
+          cend[q] = (q + 1 < gstart[g + 1] && gdesc[4 * (q + 1)] == gdesc[4 * q]) ? cend[q + 1] : q + 1;
+      int mg = 0;
+      for (int q = 0; q < ng; q++) mg = std::max(mg, (cend[q] - q) * hncol[gdesc[4 * q]]);
+      m.max_hs_class = mg;
       m.dt.pg_start.upload(gstart);
       m.dt.pg_desc.upload(gdesc);
+      m.dt.pg_cend.upload(cend);
     }
     (s == 0 ? m.dt.pj_idx : m.dt.nj_idx).upload(jidx);
     (s == 0 ? m.dt.pj_meta : m.dt.nj_meta).upload(jmeta);
