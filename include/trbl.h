@@ -79,7 +79,7 @@ typedef struct {
   int nb;          /* block size p (1..64) */
   int n_eig;       /* wanted lowest eigenpairs N */
   int l_s;         /* vectors kept at a thick restart (N <= l_s) */
-  int l_m;         /* maximum stored Lanczos vectors (l_s + 2*nb <= l_m <= D) */
+  int l_m;         /* maximum stored Lanczos vectors (l_s + 2*nb <= l_m <= D, l_m - nb <= 640) */
   int max_iter;    /* block iterations before giving up */
   double tol;      /* residual tolerance: rho_i <= tol * max|theta| */
   int precision;   /* trbl_precision */
@@ -104,7 +104,8 @@ typedef struct {
 typedef struct {
   int iterations, restarts, n_converged, breakdowns;
   double t_total, t_hv, t_orth, t_qr, t_eig, t_restart, t_refine; /* seconds (device events) */
-  double* resid;   /* optional caller host buffer of n_eig residual norms */
+  double* resid;   /* optional caller host buffer of n_eig residual norms ||H x - theta x|| of the
+                      returned pairs, computed with H itself in FP64 */
 } trbl_info;
 
 /* Build the M-scheme product basis (Sec. 2, App. A). parity: +1, -1, or 0 for both.
@@ -131,6 +132,19 @@ int trbl_basis_unrank_dev(const trbl_model* m, const int64_t* idx, int64_t n, ui
 int trbl_basis_rank_dev(const trbl_model* m, const uint64_t* pbits, const uint64_t* nbits, int64_t n,
                         int64_t* idx, void* stream);
 
+/* The seeded synthetic interaction of the benchmark workloads (a stand-in for the tabulated
+   interactions the paper uses with the Hamiltonian of Sec. 2): every independent J-coupled
+   element V_J(ab,cd) of the pp, nn and pn channels drawn i.i.d. from N(0, sigma^2), as
+   trbl_set_hamiltonian takes them. Order: channel pp, nn, pn; 2J = 0, 2, ..., 2 * (largest 2j);
+   pair parity + then -; inside a (channel, 2J, parity) block the allowed pairs (a <= b for pp
+   and nn, every (a, b) for pn; orbit order) and all pairs (i <= j) of them. Draw k is
+   sigma * sqrt(-2 ln u1) cos(2 pi u2), u1 = u(2k), u2 = u(2k + 1), u(c) = ((s >> 11) + 1) / 2^53
+   with s the c-th output of splitmix64 from state seed. Host only (no device needed).
+   out: host array of `capacity` elements, or NULL (with capacity 0) to ask for the count;
+   *n_out = the number of elements. TRBL_E_INVALID for a bad orbit or a short buffer. */
+int trbl_random_tbme(const trbl_orbit* orbits, int n_orbits, uint64_t seed, double sigma, trbl_tbme* out,
+                     int64_t capacity, int64_t* n_out);
+
 /* Set H = sum_a e_a n_a + two-body (Sec. 2). spe_p, spe_n: one energy per orbit (host).
    tbme: n_v host elements. Copies everything, builds the one-body jump and
    identical-particle tables of App. B on the device. */
@@ -154,8 +168,17 @@ int trbl_apply(const trbl_model* m, int precision, int nb, const void* V, void* 
    buffer of restarts that keep more than 208 vectors), small tables; the mixed refinement
    adds two FP64 [D][w] blocks, w = max(1, min(32, 5e8 / D)) columns (at most 8 GB together
    while D <= 5e8).
+   Before returning, every returned pair is checked against H itself: the FP64 residual
+   ||H x - theta x|| (x formed nb columns at a time when evecs is NULL) must not exceed
+   10 * tol * s + 1e-12 * s, s the largest |x^T H x| / x^T x of the returned vectors (mixed mode:
+   max(tol, 1e-5) for tol and the refined eigenvalues for s; with TRBL_CONV_RITZ_CHANGE the
+   larger of tol * s and the estimate from the projected matrix); these norms go to
+   info->resid.
    Returns TRBL_NOT_CONVERGED after max_iter iterations with the current Ritz values (NaN
-   beyond the m available when fewer than n_eig exist yet). */
+   beyond the m available when fewer than n_eig exist yet), or when a returned pair fails that
+   check (a basis the projected matrix no longer describes).
+   Testing aid: with the environment variable TRBL_TEST_CORRUPT_RESTART=1 the first restart
+   overwrites half of the first kept Ritz vector, so that the check above must fail. */
 int trbl_solve(const trbl_model* m, const trbl_opts* opts, double* evals, void* evecs, trbl_info* info);
 
 /* Gradient of sum_k w_k E_k (Hellmann-Feynman) with respect to every element of the last

@@ -28,7 +28,7 @@ def _load():
         P = ctypes.c_void_p
         i64 = ctypes.c_int64
         _lib.orc_lines.argtypes = [ctypes.c_int, P, i64, P, P, P, i64, ctypes.c_int, P, P, P, P, P, P,
-                                   P, i64, P, P, P, i64]
+                                   P, i64, P, P, P, i64, ctypes.c_int]
         _lib.orc_lines.restype = ctypes.c_int
         _lib.orc_apply_rows.argtypes = [P, i64, P, P, P, i64, ctypes.c_int, P, P, P, P, P, P, P, i64,
                                         P, ctypes.c_int, P]
@@ -89,7 +89,7 @@ class Model:
         self._colterms = self._group(lambda k: (k[2], k[3]))
         self.cap = int(max(1, len(self.terms))) + 1
 
-    def _lines(self, idx, mode):
+    def _lines(self, idx, mode, merge=1):
         lib = _load()
         idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64))
         ta, tb, tc, td, th, start = self._rowterms if mode == 0 else self._colterms
@@ -99,7 +99,7 @@ class Model:
         val = np.zeros(cap_total, dtype=np.float64)
         rc = lib.orc_lines(mode, _ptr(idx), len(idx), _ptr(self.words), _ptr(self.sorted), _ptr(self.sidx),
                            self.dim, self.S, _ptr(self.e), _ptr(ta), _ptr(tb), _ptr(tc), _ptr(td), _ptr(th),
-                           _ptr(start), self.cap, _ptr(ptr), _ptr(col), _ptr(val), cap_total)
+                           _ptr(start), self.cap, _ptr(ptr), _ptr(col), _ptr(val), cap_total, merge)
         if rc != 0:
             raise RuntimeError(f"orc_lines failed ({rc})")
         n = ptr[-1]
@@ -108,6 +108,13 @@ class Model:
     def rows(self, idx):
         """CSR pieces (ptr, col, val) of rows ``idx``: <i|H|j>."""
         return self._lines(idx, 0)
+
+    def rows_generated(self, idx):
+        """Rows ``idx`` as the terms that generate them, unmerged (ptr, col, val): the
+        single-particle-energy diagonal, then one entry per m-scheme term whose adjoint maps
+        basis state i to a basis state. A per-element H.V adds exactly these products, so
+        np.diff(ptr) is the number of terms its sum for row i has."""
+        return self._lines(idx, 0, merge=0)
 
     def columns(self, idx):
         """CSR pieces of columns ``idx``: <j|H|i>, built by applying H to |i>."""

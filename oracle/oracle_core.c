@@ -64,11 +64,13 @@ static int cmp_entry(const void* x, const void* y) {
  * terms themselves, grouped by the annihilation pair (c,d)).
  * Terms k in [start[p*S+q], start[p*S+q+1]) have group pair (p,q).
  * Returns the number of merged entries written (<= cap), or -1 if cap is too small.
+ * With merge == 0 the entries are left as generated: one per term that reaches a basis state,
+ * plus the single-particle-energy diagonal first (a per-element sum adds exactly these).
  */
 static int64_t line_entries(int mode, int64_t i, const uint64_t* words, const uint64_t* sorted,
                             const int64_t* sidx, int64_t D, int S, const double* e,
                             const int* ta, const int* tb, const int* tc, const int* td,
-                            const double* th, const int64_t* start, entry* buf, int64_t cap) {
+                            const double* th, const int64_t* start, entry* buf, int64_t cap, int merge) {
     uint64_t w = words[i];
     int64_t n = 0;
     double diag = 0.0;
@@ -96,6 +98,7 @@ static int64_t line_entries(int mode, int64_t i, const uint64_t* words, const ui
             }
         }
     }
+    if (!merge) return n;
     qsort(buf, (size_t)n, sizeof(entry), cmp_entry);
     int64_t m = 0;
     for (int64_t t = 0; t < n; t++) {
@@ -105,19 +108,20 @@ static int64_t line_entries(int mode, int64_t i, const uint64_t* words, const ui
     return m;
 }
 
-/* Rows (mode 0) or columns (mode 1) of H for the listed indices, as CSR pieces.
-   out_ptr has nlist+1 entries; returns 0, or -1 if cap_total is exceeded. */
+/* Rows (mode 0) or columns (mode 1) of H for the listed indices, as CSR pieces (merge == 0:
+   the generated terms, unmerged). out_ptr has nlist+1 entries; returns 0, or -1 if cap_total is
+   exceeded. */
 int orc_lines(int mode, const int64_t* list, int64_t nlist, const uint64_t* words,
               const uint64_t* sorted, const int64_t* sidx, int64_t D, int S, const double* e,
               const int* ta, const int* tb, const int* tc, const int* td, const double* th,
               const int64_t* start, int64_t per_line_cap, int64_t* out_ptr, int64_t* out_col,
-              double* out_val, int64_t cap_total) {
+              double* out_val, int64_t cap_total, int merge) {
     entry* buf = (entry*)malloc(sizeof(entry) * (size_t)per_line_cap);
     if (!buf) return -2;
     out_ptr[0] = 0;
     for (int64_t r = 0; r < nlist; r++) {
         int64_t m = line_entries(mode, list[r], words, sorted, sidx, D, S, e, ta, tb, tc, td, th,
-                                 start, buf, per_line_cap);
+                                 start, buf, per_line_cap, merge);
         if (m < 0 || out_ptr[r] + m > cap_total) { free(buf); return -1; }
         for (int64_t t = 0; t < m; t++) {
             out_col[out_ptr[r] + t] = buf[t].col;
@@ -146,7 +150,7 @@ int orc_apply_rows(const int64_t* list, int64_t nlist, const uint64_t* words, co
 #pragma omp for schedule(dynamic, 64)
             for (int64_t r = 0; r < nlist; r++) {
                 int64_t m = line_entries(0, list[r], words, sorted, sidx, D, S, e, ta, tb, tc, td,
-                                         th, start, buf, per_line_cap);
+                                         th, start, buf, per_line_cap, 1);
                 double* out = W + r * (int64_t)nb;
                 for (int c = 0; c < nb; c++) out[c] = 0.0;
                 if (m < 0) {
@@ -182,7 +186,7 @@ int orc_row_nnz(const int64_t* list, int64_t nlist, const uint64_t* words, const
 #pragma omp for schedule(dynamic, 256)
             for (int64_t r = 0; r < nlist; r++) {
                 int64_t m = line_entries(0, list[r], words, sorted, sidx, D, S, e, ta, tb, tc, td, th,
-                                         start, buf, per_line_cap);
+                                         start, buf, per_line_cap, 1);
                 nnz[r] = m;
                 if (m < 0) {
 #pragma omp atomic write

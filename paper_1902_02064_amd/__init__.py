@@ -80,6 +80,8 @@ def load():
         "trbl_tbme_grad": ([P, ctypes.POINTER(Opts), I, P, P, P, P], I),
         "trbl_expect": ([P, I, P, P, P], I),
         "trbl_occupation_mask": ([P, P, I, I, P, P], I),
+        "trbl_random_tbme": ([ctypes.POINTER(Orbit), I, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(Tbme), I64,
+                              ctypes.POINTER(I64)], I),
         "trbl_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -88,6 +90,18 @@ def load():
         fn.restype = res
     _lib = lib
     return lib
+
+
+def random_tbme(orbits, seed, sigma=1.0):
+    """The library's seeded synthetic interaction (trbl_random_tbme): a list of
+    (channel, a, b, c, d, 2J, v) in the library's drawing order."""
+    lib = load()
+    arr = (Orbit * len(orbits))(*[Orbit(*o) for o in orbits])
+    n = ctypes.c_int64()
+    _check(lib.trbl_random_tbme(arr, len(orbits), int(seed), float(sigma), None, 0, ctypes.byref(n)))
+    out = (Tbme * max(1, n.value))()
+    _check(lib.trbl_random_tbme(arr, len(orbits), int(seed), float(sigma), out, n.value, ctypes.byref(n)))
+    return [(t.channel, t.a, t.b, t.c, t.d, t.twoJ, t.v) for t in out[:n.value]]
 
 
 def header_symbols():
@@ -149,6 +163,7 @@ class Model:
         _check(lib.trbl_model_dim(h, ctypes.byref(d)))
         self.dim = int(d.value)
         self.n_tbme = 0
+        self.h_version = 0  # incremented by every set_hamiltonian
 
     def close(self):
         if self._h:
@@ -207,6 +222,7 @@ class Model:
                                                  int(t[5]), float(t[6])) for t in tbme])
         _check(load().trbl_set_hamiltonian(self._h, sp, sn, arr, len(tbme)))
         self.n_tbme = len(tbme)
+        self.h_version += 1
 
     def apply(self, V, W=None):
         """W = H V on the device; V is [D, nb] float64 (FP64) or float32 (mixed precision)."""
@@ -299,11 +315,16 @@ def _autograd_fn():
         @staticmethod
         def forward(ctx, v, spe_p, spe_n, model, structure, solver, keep_vectors):
             tb = [tuple(s) + (float(x),) for s, x in zip(structure, v.detach().cpu().tolist())]
-            model.set_hamiltonian(spe_p.detach().cpu().tolist(), spe_n.detach().cpu().tolist(), tb)
+            sp, sn = spe_p.detach().cpu().tolist(), spe_n.detach().cpu().tolist()
+            model.set_hamiltonian(sp, sn, tb)
             ev, X, info = model.solve(vectors=keep_vectors, **solver)
             if not info.converged:
                 raise TrblError(TRBL_NOT_CONVERGED, "TRBL did not converge in forward")
             ctx.model, ctx.solver, ctx.X = model, solver, X
+            # the Hamiltonian of this forward pass: the backward pass restores it if the model has
+            # been given another one since (a later forward pass, a finite-difference evaluation)
+            ctx.h = (sp, sn, tb)
+            ctx.h_version = model.h_version
             ctx.norb = len(model.orbits)
             return torch.from_numpy(ev).to(v.dtype)
 
@@ -311,6 +332,9 @@ def _autograd_fn():
         def backward(ctx, gE):
             w = gE.detach().cpu().numpy().astype(np.float64)
             s = ctx.solver
+            if ctx.model.h_version != ctx.h_version:
+                ctx.model.set_hamiltonian(*ctx.h)
+                ctx.h_version = ctx.model.h_version
             gv, gs = ctx.model.tbme_grad(w, evecs=ctx.X, nb=s["nb"], l_s=s.get("l_s"), l_m=s.get("l_m"),
                                          tol=s["tol"], max_iter=s.get("max_iter", 5000), seed=s.get("seed", 1000),
                                          n_solve=s["n_eig"])

@@ -1,5 +1,7 @@
 // C ABI of libtrbl (declared in include/trbl.h): argument checks, error
 // capture, and dispatch to the host set-up, the H.V kernels and the solver.
+#include <algorithm>
+#include <cmath>
 #include <cstring>
 
 #include "dense.h"
@@ -30,9 +32,70 @@ static int guarded(F&& f) {
   }
 }
 
+namespace {
+
+// The c-th output (0-based) of splitmix64 started from state `seed` (Steele, Lea and Flood,
+// OOPSLA 2014, with Vigna's finaliser constants), so any draw can be made directly.
+uint64_t splitmix64_at(uint64_t seed, uint64_t c) {
+  uint64_t z = seed + (c + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+// uniform in (0, 1]: the top 53 bits plus one unit in the last place
+double uniform01_at(uint64_t seed, uint64_t c) {
+  return ((double)(splitmix64_at(seed, c) >> 11) + 1.0) * (1.0 / 9007199254740992.0);
+}
+// standard normal number k: Box-Muller (cosine branch) on uniforms 2k and 2k + 1
+double normal_at(uint64_t seed, uint64_t k) {
+  const double u1 = uniform01_at(seed, 2 * k), u2 = uniform01_at(seed, 2 * k + 1);
+  return std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * 3.141592653589793 * u2);
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* trbl_last_error(void) { return trbl::g_last_error.c_str(); }
+
+int trbl_random_tbme(const trbl_orbit* orbits, int n_orbits, uint64_t seed, double sigma, trbl_tbme* out,
+                     int64_t capacity, int64_t* n_out) {
+  return guarded([&] {
+    TRBL_REQUIRE(orbits && n_orbits >= 1 && n_orbits <= 12 && n_out, TRBL_E_INVALID, "bad argument");
+    TRBL_REQUIRE(capacity >= 0 && (out || capacity == 0), TRBL_E_INVALID, "bad output buffer");
+    int tjmax = 0;
+    for (int o = 0; o < n_orbits; o++) {
+      TRBL_REQUIRE(orbits[o].twoj > 0 && (orbits[o].twoj & 1) && orbits[o].l >= 0, TRBL_E_INVALID, "bad orbit");
+      tjmax = std::max(tjmax, orbits[o].twoj);
+    }
+    auto allows = [&](int ch, int a, int b, int tJ) {
+      const int ja = orbits[a].twoj, jb = orbits[b].twoj;
+      if (tJ < std::abs(ja - jb) || tJ > ja + jb) return false;
+      return !(ch != 2 && a == b && ((tJ / 2) & 1));  // identical nucleons in one shell: even J
+    };
+    int64_t n = 0;
+    uint64_t k = 0;
+    std::vector<std::pair<int, int>> blk;
+    for (int ch = 0; ch < 3; ch++)
+      for (int tJ = 0; tJ <= 2 * tjmax; tJ += 2)
+        for (int par = 1; par >= -1; par -= 2) {
+          // pairs of the block: (a <= b) for pp and nn, every (a, b) for pn (a proton, b neutron)
+          blk.clear();
+          for (int a = 0; a < n_orbits; a++)
+            for (int b = (ch == 2 ? 0 : a); b < n_orbits; b++)
+              if ((((orbits[a].l + orbits[b].l) & 1) ? -1 : 1) == par && allows(ch, a, b, tJ)) blk.push_back({a, b});
+          for (size_t i = 0; i < blk.size(); i++)
+            for (size_t j = i; j < blk.size(); j++, k++, n++) {
+              if (!out) continue;
+              TRBL_REQUIRE(n < capacity, TRBL_E_INVALID, "output buffer too small");
+              out[n] = trbl_tbme{ch, blk[i].first, blk[i].second, blk[j].first, blk[j].second, tJ,
+                                 sigma * normal_at(seed, k)};
+            }
+        }
+    *n_out = n;
+    return TRBL_OK;
+  });
+}
 
 int trbl_model_create(const trbl_orbit* orbits, int n_orbits, int n_prot, int n_neut, int twoM, int parity,
                       trbl_model** out) {

@@ -53,6 +53,8 @@ void resid(const double* beta, int nb, const double* U, int ldu, int m, int n, d
 void t_restart(double* T, int ldt, int lm, const double* theta, int ls, const double* beta, int nb, const double* U,
                int ldu, int m, hipStream_t st);
 
+constexpr int EIG_NMAX = 640;  // largest projected matrix the device eigensolver takes
+
 // Symmetric eigensolver of a small dense matrix (eig.hip): all eigenvalues ascending in theta[0:n],
 // orthonormal eigenvectors of the nvec lowest in U (n x nvec, ld ldu).
 struct EigWork {
@@ -64,6 +66,11 @@ void symeig(const double* T, int ldt, int n, int nvec, double* theta, double* U,
 void gen_reduce(const double* S, const double* G, int n, double* M, double* Linv, int* status, hipStream_t st);
 // Y = L^-T Yp (n x nv, ld ldy).
 void gen_back(const double* Linv, const double* Yp, int ldp, int n, int nv, double* Y, int ldy, hipStream_t st);
+// out[c] = sum_r W[r, c] X[r, c] over D rows (device out, ncol <= 64); part holds dot_cols_parts(D) * ncol
+// doubles of partial sums
+int dot_cols_parts(int64_t D);
+void dot_cols(const double* W, int64_t ldw, const double* X, int64_t ldx, int ncol, int64_t D, double* part,
+              double* out, hipStream_t st);
 // column norms of W - X diag(theta) over D rows: out[c] (squared sums accumulated, then sqrt on host side)
 void resid_cols(const double* W, int64_t ldw, const double* X, int64_t ldx, const double* theta, int ncol, int64_t D,
                 double* out, Scratch& s, hipStream_t st);

@@ -22,7 +22,6 @@
 namespace trbl {
 
 constexpr int EIG_THREADS = 1024;
-constexpr int EIG_NMAX = 640;  // largest projected matrix (l_m)
 constexpr int PNB = 8;         // Householder panel width
 
 __device__ static double block_sum(double v, double* red) {
@@ -654,6 +653,20 @@ __global__ void resid_cols_kernel(const double* W, int64_t ldw, const double* X,
   if (rsub == 0 && c < ncol) part[(int64_t)blockIdx.x * ncol + c] = acc[0][c] + acc[1][c] + acc[2][c] + acc[3][c];
 }
 
+__global__ void dot_cols_kernel(const double* W, int64_t ldw, const double* X, int64_t ldx, int ncol, int64_t D,
+                                int64_t rows_per, double* part) {
+  const int c = threadIdx.x % 64;
+  const int rsub = threadIdx.x / 64;
+  __shared__ double acc[4][64];
+  double s = 0.0;
+  const int64_t r0 = blockIdx.x * rows_per, r1 = min(D, r0 + rows_per);
+  if (c < ncol)
+    for (int64_t r = r0 + rsub; r < r1; r += 4) s += W[r * ldw + c] * X[r * ldx + c];
+  acc[rsub][c] = s;
+  __syncthreads();
+  if (rsub == 0 && c < ncol) part[(int64_t)blockIdx.x * ncol + c] = acc[0][c] + acc[1][c] + acc[2][c] + acc[3][c];
+}
+
 void gen_reduce(const double* S, const double* G, int n, double* M, double* Linv, int* status, hipStream_t st) {
   static thread_local DevBuf Lb;
   Lb.alloc((size_t)n * n * sizeof(double));
@@ -676,6 +689,19 @@ void resid_cols(const double* W, int64_t ldw, const double* X, int64_t ldx, cons
   G = (int)((D + rows_per - 1) / rows_per);
   double* part = s.partials((size_t)G * ncol);
   hipLaunchKernelGGL(resid_cols_kernel, dim3(G), dim3(256), 0, st, W, ldw, X, ldx, theta, ncol, D, rows_per, part);
+  hipLaunchKernelGGL(reduce_partials_kernel_eig, dim3(1), dim3(64), 0, st, part, G, ncol, out);
+  TRBL_HIP(hipGetLastError());
+}
+
+int dot_cols_parts(int64_t D) { return (int)std::min<int64_t>(1024, std::max<int64_t>(1, D / 1024)); }
+
+void dot_cols(const double* W, int64_t ldw, const double* X, int64_t ldx, int ncol, int64_t D, double* part,
+              double* out, hipStream_t st) {
+  TRBL_REQUIRE(ncol >= 1 && ncol <= 64, TRBL_E_INVALID, "dot_cols: 1 to 64 columns per call");
+  int G = dot_cols_parts(D);
+  const int64_t rows_per = (D + G - 1) / G;
+  G = (int)((D + rows_per - 1) / rows_per);
+  hipLaunchKernelGGL(dot_cols_kernel, dim3(G), dim3(256), 0, st, W, ldw, X, ldx, ncol, D, rows_per, part);
   hipLaunchKernelGGL(reduce_partials_kernel_eig, dim3(1), dim3(64), 0, st, part, G, ncol, out);
   TRBL_HIP(hipGetLastError());
 }

@@ -55,7 +55,9 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
   TRBL_REQUIRE(nb >= 1 && nb <= 64, TRBL_E_INVALID, "nb must be 1..64");
   TRBL_REQUIRE(neig >= 1 && neig <= ls, TRBL_E_INVALID, "need 1 <= n_eig <= l_s");
   TRBL_REQUIRE(ls + 2 * nb <= lm && (int64_t)lm <= D, TRBL_E_INVALID, "need l_s + 2 nb <= l_m <= D");
-  TRBL_REQUIRE(lm <= 768, TRBL_E_INVALID, "l_m above 768 is not supported");
+  // the projected matrix reaches l_m - nb rows before a restart (the next block is stored first)
+  TRBL_REQUIRE(lm - nb <= EIG_NMAX, TRBL_E_INVALID,
+               "l_m - nb above " + std::to_string(EIG_NMAX) + " (the device eigensolver's largest matrix)");
   TRBL_REQUIRE(o.tol > 0.0 && o.max_iter >= 1, TRBL_E_INVALID, "bad tol or max_iter");
   TRBL_REQUIRE(o.criterion == TRBL_CONV_RESIDUAL || o.criterion == TRBL_CONV_RITZ_CHANGE, TRBL_E_INVALID,
                "unknown convergence criterion");
@@ -64,6 +66,10 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
   const double tol = mixed ? std::max(o.tol, 1e-5) : o.tol;
   const char* vb = std::getenv("TRBL_VERBOSE");
   const bool verbose = vb && vb[0] && vb[0] != '0';
+  // testing aid (trbl.h): overwrite half of the first kept Ritz vector after the first restart,
+  // a damaged basis that T cannot see, so that the check of the returned pairs must catch it
+  const char* cr = std::getenv("TRBL_TEST_CORRUPT_RESTART");
+  const bool corrupt_restart = cr && cr[0] == '1';
   const auto t_begin = std::chrono::steady_clock::now();
 
   const int64_t ldq = round4(lm);
@@ -343,6 +349,8 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
       rowgemm<TQ, TQ>(Q, ldq, mcur, U, ldu, ls, Q, ldq, D, mcur, ls, nb, st, reinterpret_cast<TQ*>(W),
                       D * nb * (int64_t)(sizeof(double) / sizeof(TQ)));
       t_restart(T, lm, lm, theta, ls, beta, nb, U, ldu, mcur, st);
+      if (corrupt_restart && restarts == 0 && ls >= 2)  // testing aid: damage a kept Ritz vector
+        copy_cols<TQ, TQ>(Q + 1, ldq, Q, ldq, D / 2, 1, st);
       TRBL_HIP(hipEventRecord(ev.e[5], st));
       TRBL_HIP(hipEventSynchronize(ev.e[5]));
       t_rst += ev.ms(4, 5);
@@ -357,10 +365,67 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
   double t_refine = 0.0;
   std::vector<double> res(rh.begin(), rh.begin() + nchk);
   for (int i = 0; i < neig; i++) evals[i] = i < nchk ? th[i] : NAN;
+  bool verified = true;
   if (!mixed || !o.refine) {
     // the convergence test may have used eigenvectors of T that were only normalised
-    if (evecs && !last_orth) symeig(T, lm, mcur, std::min(neig, mcur), theta, U, ldu, ew, true, st);
+    const int nv = std::min(neig, mcur);
+    if (!last_orth) symeig(T, lm, mcur, nv, theta, U, ldu, ew, true, st);
     if (evecs) rowgemm<TQ, double>(Q, ldq, mcur, U, ldu, neig, static_cast<double*>(evecs), neig, D, -1, 0, 0, st);
+    // The returned pairs are checked against H itself: ||H x - theta x|| in FP64 for every Ritz
+    // pair, nb columns at a time (the W block holds H X, the packed block or a new one holds X
+    // where the caller wants no vectors). rho from T equals it in exact arithmetic; a damaged
+    // basis (which T cannot see) shows up here.
+    const int w = nb;
+    DevBuf Xown;
+    double* Xc = nullptr;
+    if (!evecs) {
+      if (sizeof(TQ) == 8) Xc = reinterpret_cast<double*>(Vk);
+      else {
+        Xown.alloc((size_t)D * w * sizeof(double));
+        Xc = Xown.as<double>();
+      }
+    }
+    DevBuf rs;
+    rs.alloc((size_t)std::max(nv, 1) * 3 * sizeof(double));
+    double* xhx = rs.as<double>() + nv;   // x^T H x
+    double* xx = xhx + nv;                // x^T x
+    for (int c = 0; c < nv; c += w) {
+      const int cw = std::min(w, nv - c);
+      const double* X;
+      int64_t ldx;
+      if (evecs) {
+        X = static_cast<const double*>(evecs) + c;
+        ldx = neig;
+      } else {
+        rowgemm<TQ, double>(Q, ldq, mcur, U + c, ldu, cw, Xc, cw, D, -1, 0, 0, st);
+        X = Xc;
+        ldx = cw;
+      }
+      apply_h(TRBL_FP64, cw, X, ldx, W, cw);
+      mask_rows<double>(W, cw, D, cw, o.mask, st);
+      resid_cols(W, cw, X, ldx, theta + c, cw, D, rs.as<double>() + c, sc, st);
+      double* part = sc.partials((size_t)dot_cols_parts(D) * cw);
+      dot_cols(W, cw, X, ldx, cw, D, part, xhx + c, st);
+      dot_cols(X, ldx, X, ldx, cw, D, part, xx + c, st);
+    }
+    std::vector<double> tr(3 * (size_t)nv);
+    TRBL_HIP(hipMemcpyAsync(tr.data(), rs.p, 3 * nv * sizeof(double), hipMemcpyDeviceToHost, st));
+    TRBL_HIP(hipStreamSynchronize(st));
+    // The scale is the largest Rayleigh quotient of the returned vectors with H itself (T's own
+    // values would scale a damaged run's tolerance with the damage). Allowed: ten times the
+    // tolerance (with the Ritz-change criterion, ten times the larger of that and T's estimate),
+    // plus rounding.
+    double scale = 0.0;
+    for (int i = 0; i < nv; i++) scale = std::max(scale, std::fabs(tr[nv + i] / std::max(tr[2 * nv + i], 1e-300)));
+    for (int i = 0; i < nv; i++) {
+      tr[i] = std::sqrt(std::max(tr[i], 0.0));
+      const double est = i < (int)res.size() ? res[i] : 0.0;
+      const double base = o.criterion == TRBL_CONV_RITZ_CHANGE ? std::max(est, tol * scale) : tol * scale;
+      if (!(tr[i] <= 10.0 * base + 1e-12 * scale)) verified = false;
+    }
+    tr.resize(nv);
+    if (verbose && !verified) std::fprintf(stderr, "trbl: Ritz pairs fail the check against H\n");
+    res.assign(tr.begin(), tr.end());
   } else {
     // FP64 Rayleigh-Ritz on span(X), X = Q U[:, :n_eig] stored in place in Q's first n_eig columns
     TRBL_HIP(hipEventRecord(ev.e[0], st));
@@ -397,22 +462,45 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
     int gst = 0;
     TRBL_HIP(hipMemcpyAsync(evals, th2.as<double>(), neig * sizeof(double), hipMemcpyDeviceToHost, st));
     TRBL_HIP(hipMemcpyAsync(&gst, st2.as<int>(), sizeof(int), hipMemcpyDeviceToHost, st));
-    if (evecs) {
-      double* X = static_cast<double*>(evecs);
-      rowgemm<TQ, double>(Q, ldq, neig, Yb.as<double>(), neig, neig, X, neig, D, -1, 0, 0, st);
-      // residual norms of the refined pairs in FP64
-      DevBuf rs;
-      rs.alloc((size_t)neig * sizeof(double));
-      for (int c = 0; c < neig; c += cw) {
-        const int w = std::min(std::min(cw, 64), neig - c);
-        apply_h(TRBL_FP64, w, X + c, neig, Hc.as<double>(), w);
-        mask_rows<double>(Hc.as<double>(), w, D, w, o.mask, st);
-        resid_cols(Hc.as<double>(), w, X + c, neig, th2.as<double>() + c, w, D, rs.as<double>() + c, sc, st);
+    // residual norms of the refined pairs in FP64, against H itself (the Ritz vectors formed
+    // chunk by chunk where the caller wants none back)
+    if (evecs)
+      rowgemm<TQ, double>(Q, ldq, neig, Yb.as<double>(), neig, neig, static_cast<double*>(evecs), neig, D, -1, 0, 0,
+                          st);
+    DevBuf rs;
+    rs.alloc((size_t)neig * sizeof(double));
+    for (int c = 0; c < neig; c += cw) {
+      const int w = std::min(std::min(cw, 64), neig - c);
+      const double* X;
+      int64_t ldx;
+      if (evecs) {
+        X = static_cast<const double*>(evecs) + c;
+        ldx = neig;
+      } else {
+        rowgemm<TQ, double>(Q, ldq, neig, Yb.as<double>() + c, neig, w, Xc.as<double>(), w, D, -1, 0, 0, st);
+        X = Xc.as<double>();
+        ldx = w;
       }
-      TRBL_HIP(hipMemcpyAsync(res.data(), rs.as<double>(), neig * sizeof(double), hipMemcpyDeviceToHost, st));
-      TRBL_HIP(hipStreamSynchronize(st));
-      for (auto& x : res) x = std::sqrt(x);
+      apply_h(TRBL_FP64, w, X, ldx, Hc.as<double>(), w);
+      mask_rows<double>(Hc.as<double>(), w, D, w, o.mask, st);
+      resid_cols(Hc.as<double>(), w, X, ldx, th2.as<double>() + c, w, D, rs.as<double>() + c, sc, st);
     }
+    const std::vector<double> est = res;  // estimates from T for the unrefined pairs
+    res.assign(neig, 0.0);
+    TRBL_HIP(hipMemcpyAsync(res.data(), rs.as<double>(), neig * sizeof(double), hipMemcpyDeviceToHost, st));
+    TRBL_HIP(hipStreamSynchronize(st));
+    // scale: the refined eigenvalues are Rayleigh-Ritz values of H itself
+    std::vector<double> th2h(neig);
+    TRBL_HIP(hipMemcpy(th2h.data(), th2.p, neig * sizeof(double), hipMemcpyDeviceToHost));
+    double scale = 0.0;
+    for (double t : th2h) scale = std::max(scale, std::fabs(t));
+    for (int i = 0; i < neig; i++) {
+      res[i] = std::sqrt(std::max(res[i], 0.0));
+      const double e = i < (int)est.size() ? est[i] : 0.0;
+      const double base = o.criterion == TRBL_CONV_RITZ_CHANGE ? std::max(e, tol * scale) : tol * scale;
+      if (!(res[i] <= 10.0 * base + 1e-12 * scale)) verified = false;
+    }
+    if (verbose && !verified) std::fprintf(stderr, "trbl: refined pairs fail the check against H\n");
     TRBL_HIP(hipEventRecord(ev.e[1], st));
     TRBL_HIP(hipStreamSynchronize(st));
     TRBL_REQUIRE(gst == 0, TRBL_E_BREAKDOWN, "refinement Gram matrix not positive definite");
@@ -436,7 +524,7 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
     if (info->resid)
       for (int i = 0; i < neig; i++) info->resid[i] = i < (int)res.size() ? res[i] : NAN;
   }
-  return converged ? TRBL_OK : TRBL_NOT_CONVERGED;
+  return converged && verified ? TRBL_OK : TRBL_NOT_CONVERGED;
 }
 
 int solve(const Model& m, const trbl_opts& o, double* evals, void* evecs, trbl_info* info) {

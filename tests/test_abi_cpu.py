@@ -19,3 +19,43 @@ def test_last_error_without_gpu_call():
     rc = lib.trbl_model_dim(None, None)
     assert rc == -1
     assert b"NULL" in lib.trbl_last_error()
+
+
+def test_random_tbme_matches_the_workload_generator():
+    """trbl_random_tbme (host only) draws the interaction of the workloads: the same elements in
+    the same order, values bit-for-bit equal to the generator's formula evaluated with the C
+    library's log and cos, and within 2 ulp of the vectorised numpy evaluation (numpy's SIMD
+    log/cos may differ from the C library's by one unit in the last place)."""
+    import math
+
+    import numpy as np
+
+    from workloads import PF_ORBITS, SD_ORBITS, SNSB_ORBITS, random_tbme, uniform01
+    for orbits in (SD_ORBITS, PF_ORBITS, SNSB_ORBITS):
+        for seed in (1, 2, 3):
+            lib_t = trbl.random_tbme(orbits, seed, 1.0)
+            ref = random_tbme(orbits, seed, 1.0)
+            assert len(lib_t) == len(ref)
+            for k, (a, b) in enumerate(zip(lib_t, ref)):
+                assert a[:6] == b[:6]
+                u1 = float(uniform01(seed, np.array([2 * k], dtype=np.uint64))[0])
+                u2 = float(uniform01(seed, np.array([2 * k + 1], dtype=np.uint64))[0])
+                assert a[6] == math.sqrt(-2.0 * math.log(u1)) * math.cos(2.0 * math.pi * u2)
+                assert abs(a[6] - b[6]) <= 2 * np.spacing(abs(b[6]))
+    assert len(trbl.random_tbme(SD_ORBITS, 1)) == 158  # 30 pp + 30 nn + 98 pn
+    assert len(trbl.random_tbme(PF_ORBITS, 1)) == 94 + 94 + 330
+    # sigma scales every draw
+    s2 = trbl.random_tbme(SD_ORBITS, 2, 2.5)
+    s1 = trbl.random_tbme(SD_ORBITS, 2, 1.0)
+    assert all(x[6] == 2.5 * y[6] for x, y in zip(s2, s1))
+
+
+def test_random_tbme_errors():
+    lib = trbl.load()
+    arr = (trbl.Orbit * 1)(trbl.Orbit(0, 3, 7))
+    n = ctypes.c_int64()
+    assert lib.trbl_random_tbme(arr, 1, 1, 1.0, None, 0, ctypes.byref(n)) == 0 and n.value > 0
+    out = (trbl.Tbme * 1)()
+    assert lib.trbl_random_tbme(arr, 1, 1, 1.0, out, 1, ctypes.byref(n)) == -1  # buffer too small
+    bad = (trbl.Orbit * 1)(trbl.Orbit(0, 3, 6))  # even 2j
+    assert lib.trbl_random_tbme(bad, 1, 1, 1.0, None, 0, ctypes.byref(n)) == -1

@@ -10,7 +10,7 @@ import os
 import numpy as np
 import pytest
 
-from gpu_common import fp32_bound, fp64_bound, pair, say
+from gpu_common import pair, say, term_bound
 from oracle.hamiltonian import Model as OracleModel
 from workloads import SD_ORBITS, SNSB_ORBITS, WORKLOADS, jsquared_spe, jsquared_tbme, random_block, random_tbme
 
@@ -46,18 +46,19 @@ def test_fly_matches_dense_oracle(case):
     g, o = _forced(orbits, z, n, twoM, tb, spe, par)
     assert g.dim == o.dim
     H = o.dense()
-    nnz = int(np.max(np.count_nonzero(H, axis=1)))
+    rows = np.arange(o.dim)
     V = random_block(200 + seed, o.dim, nb)
     ref = H @ V
     W = g.apply(torch.from_numpy(V).cuda()).cpu().numpy()
-    bound = fp64_bound(np.abs(H) @ np.abs(V), nnz)
-    say("fp64 max err / bound", np.max(np.abs(W - ref) / (bound + 1e-300)))
-    assert np.all(np.abs(W - ref) <= 4 * bound)
+    bound = term_bound(o, rows, V)
+    say("fp64 max err / bound", np.max(np.abs(W - ref) / bound))
+    assert np.all(np.abs(W - ref) <= bound)
     V32 = V.astype(np.float32)
     W32 = g.apply(torch.from_numpy(V32).cuda()).cpu().numpy()
     ref32 = H @ V32.astype(np.float64)
-    b32 = fp32_bound(np.abs(H) @ np.abs(V32.astype(np.float64)), nnz)
-    assert np.all(np.abs(W32 - ref32) <= 4 * b32)
+    b32 = term_bound(o, rows, V32, fp32=True)
+    say("fp32 max err / bound", np.max(np.abs(W32 - ref32) / b32))
+    assert np.all(np.abs(W32 - ref32) <= b32)
 
 
 def test_fly_same_as_staged_path():
@@ -91,13 +92,10 @@ def test_sn112_sampled_rows(sn112):
     rows = np.unique(np.concatenate([[0, 1, g.dim - 2, g.dim - 1],
                                      np.random.default_rng(5).integers(0, g.dim, 300)]))
     ref = o.apply_rows(V, rows)
-    nnz = o.row_nnz(rows)
-    ptr, col, val = o.rows(rows)
-    absref = np.stack([np.abs(val[ptr[i]:ptr[i + 1]]) @ np.abs(V[col[ptr[i]:ptr[i + 1]]]) for i in range(len(rows))])
-    bound = fp64_bound(absref, int(nnz.max()))
+    bound = term_bound(o, rows, V)
     err = np.abs(W[rows] - ref)
-    say("sn112 rows", len(rows), "max nnz", nnz.max(), "max err/bound", np.max(err / (bound + 1e-300)))
-    assert np.all(err <= 4 * bound)
+    say("sn112 rows", len(rows), "max err/bound", np.max(err / bound))
+    assert np.all(err <= bound)
 
 
 def test_sn112_solve_ritz_pairs(sn112):

@@ -185,3 +185,30 @@ def test_grad_sd66_finite_differences():
         say("sd66 element", t, tb[t][:6], "fd", fd, "grad", gv[t])
         assert abs(fd - gv[t]) <= 1e-5 * max(abs(gv[t]), 1e-3 * np.abs(gv).max())
     g.set_hamiltonian(w.spe, w.spe, tb)
+
+
+def test_autograd_backward_after_another_forward(sd22):
+    """Backward of a first forward pass run after a second forward pass (another interaction) on
+    the same model, eigenvectors recomputed: the gradient is the first interaction's (the
+    backward pass restores the Hamiltonian it was taken at)."""
+    import paper_1902_02064_amd as trbl
+    w, tb, g, o = sd22
+    n = 4
+    wt = grad_weights(n, 11)
+    v1 = torch.tensor([t[6] for t in tb], dtype=torch.float64, requires_grad=True)
+    sp = torch.tensor(w.spe, dtype=torch.float64)
+    sn = torch.tensor(w.spe, dtype=torch.float64)
+    E1 = trbl.eigenvalues(g, tb, v1, sp, sn, nb=4, n_eig=n, l_s=12, l_m=40, tol=1e-11, keep_vectors=False)
+    tb2 = random_tbme(SD_ORBITS, 17)
+    v2 = torch.tensor([t[6] for t in tb2], dtype=torch.float64, requires_grad=True)
+    E2 = trbl.eigenvalues(g, tb2, v2, sp, sn, nb=4, n_eig=n, l_s=12, l_m=40, tol=1e-11, keep_vectors=False)
+    (torch.from_numpy(wt) * E1).sum().backward()
+    ov, _, e1 = _oracle_grad(o, tb, n, wt)
+    say("max diff after a second forward", np.abs(v1.grad.numpy() - ov).max())
+    assert np.abs(E1.detach().numpy() - e1).max() <= 1e-9 * np.abs(e1).max()
+    assert np.abs(v1.grad.numpy() - ov).max() <= 1e-8 * np.abs(ov).max()
+    # and the second pass's gradient is still its own
+    (torch.from_numpy(wt) * E2).sum().backward()
+    o2 = o.with_interaction(tb2, w.spe, w.spe)
+    ov2, _, _ = _oracle_grad(o2, tb2, n, wt)
+    assert np.abs(v2.grad.numpy() - ov2).max() <= 1e-8 * np.abs(ov2).max()

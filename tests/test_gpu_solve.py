@@ -168,3 +168,44 @@ def test_ritz_vectors_carry_good_angular_momentum(sd22):
     J = (-1 + np.sqrt(1 + 4 * j2)) / 2
     say("sd22 <J^2>", np.round(j2, 6))
     assert np.abs(J - np.round(J)).max() <= 1e-6
+
+
+def test_lm_beyond_the_eigensolver_is_rejected_first():
+    """l_m - nb above the device eigensolver's 640 is an argument error, reported before any
+    iteration (sd66: l_m = 700, nb = 8)."""
+    import paper_1902_02064_amd as trbl
+    w = WORKLOADS["sd66"]
+    g, _ = pair(w.orbits, w.n_prot, w.n_neut, w.twoM, w.tbme(), w.spe, w.spe, oracle=False)
+    with pytest.raises(trbl.TrblError) as ex:
+        g.solve(8, 20, 40, 700, 1e-8, "fp64")
+    assert ex.value.code == -1 and "640" in str(ex.value)
+    # the largest allowed l_m still solves
+    ev, _, info = g.solve(8, 20, 40, 648, 1e-8, "fp64", max_iter=3)
+    assert info.iterations == 3
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_returned_pairs_are_checked_against_h(sd22, prec):
+    """Every returned pair is checked with H itself: the residual norms reported are those of
+    ||H x - theta x|| (here against the dense H), and a basis damaged after the first restart
+    (the testing aid TRBL_TEST_CORRUPT_RESTART: half of a kept Ritz vector overwritten, which the
+    projected matrix cannot see) is reported as not converged instead of as a result."""
+    import os
+    w, g, o, H, e = sd22
+    ev, X, info = g.solve(w.nb, w.n_eig, w.l_s, w.l_m, w.tol, prec, vectors=True)
+    assert info.converged
+    Xh = X.cpu().numpy()
+    res = np.linalg.norm(H @ Xh - Xh * ev, axis=0)
+    say(prec, "reported", info.resid.max(), "dense", res.max())
+    assert np.allclose(info.resid, res, rtol=1e-6, atol=1e-12 * np.abs(e).max())
+    os.environ["TRBL_TEST_CORRUPT_RESTART"] = "1"
+    try:
+        for vec in (True, False):
+            ev2, _, info2 = g.solve(w.nb, w.n_eig, w.l_s, w.l_m, w.tol, prec, vectors=vec)
+            say(prec, "corrupted: converged", info2.converged, "resid", info2.resid.max())
+            assert info2.restarts >= 1 and not info2.converged
+            assert info2.resid.max() > 10 * max(w.tol, 1e-5 if prec == "mixed" else 0.0) * np.abs(e).max()
+    finally:
+        del os.environ["TRBL_TEST_CORRUPT_RESTART"]
+    ev3, _, info3 = g.solve(w.nb, w.n_eig, w.l_s, w.l_m, w.tol, prec)
+    assert info3.converged and np.array_equal(ev3, ev)

@@ -221,3 +221,87 @@ def test_hermitian_trace_and_sparse_rows():
     V = rng.standard_normal((m.dim, 3))
     idx = rng.choice(m.dim, 50, replace=False)
     assert np.allclose(m.apply_rows(V, idx), (H @ V)[idx], atol=1e-12)
+
+
+def _move_linked_pairs(words):
+    """Pairs (i, j) of basis states whose occupations differ by at most two particles moved
+    (i == j included): every pair a one- plus two-body H can link, allowed J or not."""
+    w = np.asarray(words, dtype=np.uint64)
+    cnt = 0
+    for x in w:
+        diff = np.bitwise_xor(w, x)
+        nbits = np.array([bin(int(d)).count("1") for d in diff])
+        cnt += int(np.count_nonzero(nbits <= 4))  # a move clears one bit and sets another
+    return cnt
+
+
+@pytest.mark.parametrize("orbits,z,n,twoM,seed,nnz", [
+    (SD_ORBITS, 2, 2, 0, 1, 54112),   # sd22 workload: 54,112 = non-zeros of H
+    (SD_ORBITS, 3, 2, 1, 4, None),    # odd A
+])
+def test_row_nnz_counts_the_nonzeros(orbits, z, n, twoM, seed, nnz):
+    """Model.row_nnz (the structural count behind the H.V flop count) counts, per row, the
+    distinct columns some term reaches, diagonal included: the non-zeros of H, plus entries whose
+    terms cancel exactly (none in sd22; two in this odd-A space). Pairs linked by a move of at
+    most two particles but with no common allowed J (sd22: 54,624 such pairs) have no matrix
+    element and are not counted."""
+    tb = random_tbme(orbits, seed)
+    m = Model(orbits, z, n, twoM, tb, SD_SPE, SD_SPE)
+    H = m.dense()
+    rn = m.row_nnz()
+    nz = np.count_nonzero(H, axis=1)
+    ptr, col, val = m.rows(np.arange(m.dim))
+    zeros = np.add.reduceat((val == 0.0).astype(np.int64), ptr[:-1])
+    assert np.array_equal(rn, nz + zeros)
+    if nnz is not None:
+        assert rn.sum() == nnz and zeros.sum() == 0
+    linked = _move_linked_pairs(m.words)
+    assert linked >= rn.sum()
+    if nnz is not None:
+        assert linked == 54624
+
+
+def test_rows_generated_are_the_term_applications():
+    """rows_generated lists, per row, the single-particle diagonal plus one entry per m-scheme
+    term whose adjoint maps the row's state into the basis: pinned against a pure-Python
+    application of every term to every state, and merged it gives rows()."""
+    orbits = SD_ORBITS
+    tb = random_tbme(orbits, 6)
+    m = Model(orbits, 2, 1, 1, tb, SD_SPE, SD_SPE)
+    terms = mscheme_terms(orbits, tb)
+    words = [int(x) for x in m.words]
+    index = {w: i for i, w in enumerate(words)}
+
+    def op(w, s, create, sign):
+        bit = 1 << s
+        if bool(w & bit) == create:
+            return None, sign
+        sign *= -1 if bin(w & (bit - 1)).count("1") % 2 else 1
+        return (w | bit) if create else (w & ~bit), sign
+
+    ptr, col, val = m.rows_generated(np.arange(m.dim))
+    for i, w in enumerate(words):
+        expect = []
+        for (a, b, c, d), h in terms.items():
+            # adjoint of c+_a c+_b c_d c_c acting on <i|: remove a and b, then create d and c
+            x, sg = w, 1
+            for s, cr in ((a, False), (b, False), (d, True), (c, True)):
+                x, sg = op(x, s, cr, sg)
+                if x is None:
+                    break
+            if x is not None and x in index:
+                expect.append((index[x], sg * h))
+        got = sorted(zip(col[ptr[i] + 1:ptr[i + 1]].tolist(), val[ptr[i] + 1:ptr[i + 1]].tolist()))
+        assert col[ptr[i]] == i  # the one-body diagonal comes first
+        assert len(got) == len(expect)
+        for (cg_, vg), (ce, ve) in zip(got, sorted(expect)):
+            assert cg_ == ce and abs(vg - ve) <= 1e-14 * max(1.0, abs(ve))
+    # merged by column, the generated entries are the rows of H
+    pr, cr_, vr = m.rows(np.arange(m.dim))
+    for i in range(m.dim):
+        acc = {}
+        for j, v in zip(col[ptr[i]:ptr[i + 1]], val[ptr[i]:ptr[i + 1]]):
+            acc[int(j)] = acc.get(int(j), 0.0) + v
+        assert sorted(acc) == cr_[pr[i]:pr[i + 1]].tolist()
+        for j, v in zip(cr_[pr[i]:pr[i + 1]], vr[pr[i]:pr[i + 1]]):
+            assert abs(acc[int(j)] - v) <= 1e-13 * max(1.0, abs(v))
