@@ -196,6 +196,18 @@ int trbl_tbme_grad(const trbl_model* m, const trbl_opts* opts, int n_eig, const 
    elements) this gives <J^2> of Ritz vectors. Allocates one [D][min(n,64)] FP64 block. */
 int trbl_expect(const trbl_model* m, int n, const void* X, double* out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+   loops): trbl_expect without any allocation. out is a DEVICE array of n doubles, written on
+   `stream` (nothing is copied to the host and nothing waits). The work blocks come from a
+   static device buffer of 64 MiB that the library holds on each GPU it runs on until the
+   process ends; every call on one GPU shares it, so calls that overlap on one GPU race (order
+   them on one stream). The columns go through products of 16, 8, 4, 2 or 1 of them (the widest
+   whose D x width FP64 block fits the buffer), whose plans trbl_set_hamiltonian prepares.
+   TRBL_E_INVALID when D exceeds the buffer (about 8.3 million states at one column), for
+   single-species spaces generated per element, or for bad arguments; TRBL_E_STATE without a
+   Hamiltonian. The model's device must be current. */
+int trbl_expect_noalloc(const trbl_model* m, int n, const void* X, double* out, void* stream);
+
 /* Particle-hole truncation of Sec. 4.2 (e.g. at most 4 nucleons above the N = 64 subshell gap):
    mask[i] = 1.0 if basis state i has at most max_particles nucleons (protons plus neutrons) in
    the orbits orbit_set[0 .. n_set-1] (host array of orbit indices), else 0.0. mask: device [D]

@@ -79,6 +79,7 @@ def load():
         "trbl_solve": ([P, ctypes.POINTER(Opts), P, P, ctypes.POINTER(Info)], I),
         "trbl_tbme_grad": ([P, ctypes.POINTER(Opts), I, P, P, P, P], I),
         "trbl_expect": ([P, I, P, P, P], I),
+        "trbl_expect_noalloc": ([P, I, P, P, P], I),
         "trbl_occupation_mask": ([P, P, I, I, P, P], I),
         "trbl_random_tbme": ([ctypes.POINTER(Orbit), I, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(Tbme), I64,
                               ctypes.POINTER(I64)], I),
@@ -244,6 +245,15 @@ class Model:
         X = X.contiguous()
         out = np.zeros(X.shape[1])
         _check(load().trbl_expect(self._h, X.shape[1], _ptr(X), out.ctypes.data_as(ctypes.c_void_p), _stream()))
+        return out
+
+    def expect_noalloc(self, X, out):
+        """<x_c|H|x_c> into the device tensor out (float64, n) without any device allocation by the
+        library (trbl_expect_noalloc); X is device [D][n] float64, contiguous."""
+        import torch
+        assert X.is_cuda and X.dtype == torch.float64 and X.dim() == 2 and X.shape[0] == self.dim
+        assert X.is_contiguous() and out.is_cuda and out.dtype == torch.float64 and out.numel() >= X.shape[1]
+        _check(load().trbl_expect_noalloc(self._h, X.shape[1], _ptr(X), _ptr(out), _stream()))
         return out
 
     # -- eigensolver

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "dense.h"
 
@@ -32,6 +33,11 @@ static int guarded(F&& f) {
   }
 }
 
+namespace trbl {
+// the static scratch of trbl_expect_noalloc (64 MiB; see device_scratch below)
+__device__ __align__(256) char scratch[(size_t)64 << 20];
+}  // namespace trbl
+
 namespace {
 
 // The c-th output (0-based) of splitmix64 started from state `seed` (Steele, Lea and Flood,
@@ -51,6 +57,31 @@ double normal_at(uint64_t seed, uint64_t k) {
   const double u1 = uniform01_at(seed, 2 * k), u2 = uniform01_at(seed, 2 * k + 1);
   return std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * 3.141592653589793 * u2);
 }
+
+// Scratch of trbl_expect_noalloc: one static array per device (the loader places a copy on each
+// GPU the library runs on, held until the process ends). Host code never uses the array's name
+// as an address: the device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t NOALLOC_BYTES = (size_t)64 << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+char* scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+char* device_scratch() {
+  int dev = 0;
+  TRBL_HIP(hipGetDevice(&dev));
+  TRBL_REQUIRE(dev >= 0 && dev < NOALLOC_MAX_DEVICES, TRBL_E_INVALID, "device index out of range");
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void* p = nullptr;
+    TRBL_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(trbl::scratch)));
+    TRBL_REQUIRE(p != nullptr, TRBL_E_DEVICE, "no device address for the static scratch");
+    scratch_dev[dev] = static_cast<char*>(p);
+  }
+  return scratch_dev[dev];
+}
+
+// column counts whose product plans trbl_set_hamiltonian prepares for trbl_expect_noalloc
+constexpr int NOALLOC_WIDTHS[] = {1, 2, 4, 8, 16};
 
 }  // namespace
 
@@ -196,6 +227,7 @@ int trbl_set_hamiltonian(trbl_model* h, const double* spe_p, const double* spe_n
   return guarded([&] {
     TRBL_REQUIRE(h != nullptr, TRBL_E_INVALID, "NULL model");
     trbl::build_hamiltonian(h->m, spe_p, spe_n, tbme, n_v);
+    trbl::prepare_hv_plans(h->m, TRBL_FP64, NOALLOC_WIDTHS, (int)(sizeof(NOALLOC_WIDTHS) / sizeof(int)));
     return TRBL_OK;
   });
 }
@@ -228,6 +260,38 @@ int trbl_expect(const trbl_model* h, int n, const void* X, double* out, void* st
       TRBL_HIP(hipMemcpyAsync(ch.data(), Cb.p, (size_t)w * w * sizeof(double), hipMemcpyDeviceToHost, s));
       TRBL_HIP(hipStreamSynchronize(s));
       for (int j = 0; j < w; j++) out[c0 + j] = ch[(size_t)j * w + j];
+    }
+    return TRBL_OK;
+  });
+}
+
+int trbl_expect_noalloc(const trbl_model* h, int n, const void* X, double* out, void* stream) {
+  return guarded([&] {
+    TRBL_REQUIRE(h && X && out && n >= 1, TRBL_E_INVALID, "bad argument");
+    const trbl::Model& m = h->m;
+    TRBL_REQUIRE(m.has_h, TRBL_E_STATE, "no Hamiltonian set");
+    TRBL_REQUIRE(!m.fly, TRBL_E_INVALID, "single-species spaces generated per element keep work blocks; use trbl_expect");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t D = m.dim;
+    static_assert(sizeof(trbl::scratch) == NOALLOC_BYTES, "scratch size");
+    const size_t part_bytes = (size_t)trbl::dot_cols_parts(D) * 16 * sizeof(double);
+    auto hx_bytes = [&](int w) { return ((size_t)D * w * sizeof(double) + 255) / 256 * 256; };
+    // widest power-of-two chunk whose H X block fits the scratch beside the partial sums
+    int w = 16;
+    while (w > 1 && hx_bytes(w) + part_bytes > NOALLOC_BYTES) w >>= 1;
+    TRBL_REQUIRE(hx_bytes(1) + part_bytes <= NOALLOC_BYTES, TRBL_E_INVALID,
+                 "dimension too large for the " + std::to_string(NOALLOC_BYTES >> 20) + " MiB static scratch");
+    char* sc = device_scratch();
+    double* HX = reinterpret_cast<double*>(sc);
+    double* part = reinterpret_cast<double*>(sc + hx_bytes(w));
+    const double* Xd = static_cast<const double*>(X);
+    for (int c0 = 0; c0 < n;) {
+      int cw = w;
+      while (cw > n - c0) cw >>= 1;  // the remainder in power-of-two pieces: plans exist for those
+      TRBL_REQUIRE(trbl::has_hv_plan(m, TRBL_FP64, cw), TRBL_E_STATE, "product plan missing");
+      trbl::launch_apply(m, TRBL_FP64, cw, Xd + c0, n, HX, cw, s);
+      trbl::dot_cols(HX, cw, Xd + c0, n, cw, D, part, out + c0, s);
+      c0 += cw;
     }
     return TRBL_OK;
   });

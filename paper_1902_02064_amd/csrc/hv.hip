@@ -185,6 +185,17 @@ static void run_hv(const Model& m, int nb, const void* V, int64_t ldv, void* W, 
   dispatch_hv<T>(a, P, s);
 }
 
+void prepare_hv_plans(const Model& m, int precision, const int* widths, int n) {
+  if (m.fly) return;
+  for (int k = 0; k < n; k++) (void)plan_for(m, widths[k], precision == TRBL_FP64 ? sizeof(double) : sizeof(float));
+}
+
+bool has_hv_plan(const Model& m, int precision, int nb) {
+  if (m.fly) return false;
+  const int key = nb * 16 + (precision == TRBL_FP64 ? (int)sizeof(double) : (int)sizeof(float));
+  return m.hv_plans.find(key) != m.hv_plans.end();
+}
+
 void launch_apply(const Model& m, int precision, int nb, const void* V, int64_t ldv, void* W, int64_t ldw,
                   hipStream_t s) {
   TRBL_REQUIRE(m.has_h, TRBL_E_STATE, "no Hamiltonian set");

@@ -207,6 +207,10 @@ double clebsch(int tj1, int tm1, int tj2, int tm2, int tJ, int tM);
 void launch_apply(const Model& m, int precision, int nb, const void* V, int64_t ldv, void* W, int64_t ldw,
                   hipStream_t s);
 void launch_rank(const Model& m, const uint64_t* pb, const uint64_t* nb, int64_t n, int64_t* idx, hipStream_t s);
+// build the block-product plans of the given column counts now (device tables of the work
+// decomposition), so that later products of those widths allocate nothing
+void prepare_hv_plans(const Model& m, int precision, const int* widths, int n);
+bool has_hv_plan(const Model& m, int precision, int nb);
 void launch_unrank(const Model& m, const int64_t* idx, int64_t n, uint64_t* pb, uint64_t* nb, hipStream_t s);
 void launch_occupation_mask(const Model& m, const int* orbit_set, int n_set, int maxp, double* mask, hipStream_t s);
 
