@@ -68,6 +68,14 @@ def normal(seed: int, index: np.ndarray) -> np.ndarray:
     return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * math.pi * u2)
 
 
+def normal_scalar(seed: int, k: int) -> float:
+    """normal(seed, k) evaluated one draw at a time with the C library's log and cos (numpy's
+    vectorised log and cos may differ from them by one unit in the last place)."""
+    u1 = ((splitmix64(seed, 2 * k) >> 11) + 1.0) * (1.0 / 9007199254740992.0)
+    u2 = ((splitmix64(seed, 2 * k + 1) >> 11) + 1.0) * (1.0 / 9007199254740992.0)
+    return math.sqrt(-2.0 * math.log(u1)) * math.cos(2.0 * math.pi * u2)
+
+
 def random_block(seed: int, rows: int, cols: int) -> np.ndarray:
     """A rows x cols row-major block of standard normals; entry (i, c) is normal #(i*cols+c)."""
     idx = np.arange(rows * cols, dtype=np.uint64)
@@ -111,14 +119,14 @@ def random_tbme(orbits, seed: int, sigma: float = 1.0):
 
     Returns a list of (channel, a, b, c, d, 2J, v) drawn in block order
     (channel, 2J, parity +/-) and, inside a block, over pairs i<=j of the
-    block's pair list; draw number k uses normal(seed, k).
+    block's pair list; draw number k uses normal_scalar(seed, k).
     """
     out = []
     k = 0
     for ch, twoJ, _par, blk in tbme_blocks(orbits):
         for i in range(len(blk)):
             for j in range(i, len(blk)):
-                v = float(sigma * normal(seed, np.array([k], dtype=np.uint64))[0])
+                v = sigma * normal_scalar(seed, k)
                 k += 1
                 (a, b), (c, d) = blk[i], blk[j]
                 out.append((ch, a, b, c, d, twoJ, v))
