@@ -40,9 +40,11 @@ static HVPlan& plan_for(const Model& m, int nb, size_t elt) {
   // TRBL_HV_XL=0: tiles sized for the 72 KB double buffer only, for comparison
   static const size_t row_cap =
       std::getenv("TRBL_HV_XL") && std::atoi(std::getenv("TRBL_HV_XL")) == 0 ? ROW_LARGE : ROW_XL;
-  // a row buffer holds the widest source row plus the zero row of the rows kernel
-  while (C > cmin && (size_t)(m.max_dn + 1) * C * elt > row_cap) C >>= 1;
-  TRBL_REQUIRE((size_t)(m.max_dn + 1) * C * elt <= row_cap, TRBL_E_INVALID, "neutron sector too large for the LDS row tile");
+  // a row buffer holds the widest source row plus the zero rows of the rows kernel (one per
+  // part of a 256-byte bank window)
+  auto zrows = [&](int c) { return (size_t)std::max<size_t>(1, 256 / (c * elt)); };
+  while (C > cmin && (m.max_dn + zrows(C)) * C * elt > row_cap) C >>= 1;
+  TRBL_REQUIRE((m.max_dn + zrows(C)) * C * elt <= row_cap, TRBL_E_INVALID, "neutron sector too large for the LDS row tile");
   // the columns kernel stages whole proton columns: its own, possibly narrower, tile
   int Cc = C;
   while (Cc > cmin && (size_t)m.max_dp * rs_of(Cc, elt) * elt > 144 * 1024) Cc >>= 1;
@@ -70,7 +72,7 @@ static HVPlan& plan_for(const Model& m, int nb, size_t elt) {
     }
     const int nthr = std::min(1024, (dn + 63) / 64 * 64);
     const int ntb = nthr <= 256 ? 256 : nthr <= 768 ? 768 : 1024;
-    const size_t need = (size_t)(widest + 1) * C * elt;
+    const size_t need = (widest + zrows(C)) * C * elt;
     const int rb = need <= ROW_SMALL ? 24 : need <= ROW_MID ? 36 : need <= ROW_LARGE ? 72 : 144;
     members[{ntb, rb}].push_back((int)b);
   }

@@ -18,11 +18,13 @@
 // target neutron n'). The source rows V[p, :, tile] of its proton jumps are
 // streamed through two LDS buffers: while the lanes gather from one buffer,
 // the next source row is copied into the other by the global->LDS DMA of
-// gfx950 (no registers involved). Rows are stored plainly; a lane reads the
-// 16-byte chunks of a row starting at chunk (lane mod chunks-per-row), so the
-// lanes of a wavefront that gather from random rows still hit different LDS
-// banks at each step. Accumulator slot t of lane l therefore holds column chunk
-// (t + l) mod chunks-per-row, which the final store undoes.
+// gfx950 (no registers involved). Rows are stored plainly. A 16-byte LDS read
+// of a wavefront is served half a wavefront at a time, at two lanes per
+// 16-byte position of the 256-byte bank window when no position is shared by
+// more: lane l reads chunk t ^ (l mod chunks-per-row) of its row at step t
+// (accumulator slot t holds that chunk, which the final store undoes), and the
+// host orders each lane's neutron jumps so that the rows of the lanes reading
+// one chunk position fall in different parts of the window.
 #pragma once
 #include <type_traits>
 
@@ -125,7 +127,15 @@ struct Tile {
   static_assert(CPR >= 1 && (CPR & (CPR - 1)) == 0, "tile width must be a power-of-two number of chunks");
   __device__ static __forceinline__ int at(int r, int k) { return r * RB + (k << 4); }
   __device__ static __forceinline__ int rot() { return (int)threadIdx.x & (CPR - 1); }  // chunk order of this lane
+  // rows per 256-byte LDS bank window, and so the zero rows kept (one per part of the window)
+  static constexpr int NZ = RB >= 256 ? 1 : 256 / RB;
 };
+
+// The part of the bank window (source row mod 16, lowest bit most significant) that the lane
+// at position l of its sector prefers; the neutron jump lists are ordered for it on the host.
+__device__ __forceinline__ int bank_pref(int l) {
+  return ((l & 1) << 3) | ((l & 2) << 1) | ((l & 4) >> 1) | ((l & 8) >> 3);
+}
 
 // Asynchronous copy of nrows rows (C values each, row stride ld) into the tile by the
 // global->LDS DMA of buffer loads: each lane moves one 16-byte chunk per instruction and the
@@ -276,10 +286,10 @@ __global__ __launch_bounds__(NTB) void hv_rows_kernel(HVArgs<T> a) {
   using L = Tile<T, C>;
   constexpr int RBYTES = RBKB * 1024;
   constexpr int HSN = hs_bytes(RBKB, SB) / (int)sizeof(T);
-  constexpr int ZROW = RBYTES / L::RB - 1;  // the zero row of each buffer
-  static_assert(ZROW < 65536, "row index must fit the packed jumps");
-  __shared__ __align__(16) char B0[RBYTES];
-  __shared__ __align__(16) char B1[SB ? 16 : RBYTES];
+  constexpr int ZBASE = RBYTES / L::RB - L::NZ;  // the zero rows of each buffer: ZBASE .. ZBASE + NZ - 1
+  static_assert(ZBASE + L::NZ - 1 < 65536, "row index must fit the packed jumps");
+  __shared__ __align__(256) char B0[RBYTES];
+  __shared__ __align__(256) char B1[SB ? 16 : RBYTES];
   __shared__ __align__(16) T HS[HSN];
   const int64_t nitems = a.bin_item0[a.bin_nblk];
   const int64_t item = xcd_item(blockIdx.x, nitems);
@@ -323,9 +333,9 @@ __global__ __launch_bounds__(NTB) void hv_rows_kernel(HVArgs<T> a) {
   GroupIt it = group_at(a, b, ldu(a.pg_start, gp), gend);
   stage_row(B0, off + (int64_t)pl * dn, dn);
   if (!SB && it.cls < ncl) stage_row(B1, a.blk_off[it.sb] + (int64_t)it.p * a.blk_dn[it.sb], a.blk_dn[it.sb]);
-  for (int k = tid; k < L::CPR; k += nthr) {  // the zero rows (above every staged row)
-    *reinterpret_cast<float4*>(B0 + ZROW * L::RB + (k << 4)) = make_float4(0.f, 0.f, 0.f, 0.f);
-    if constexpr (!SB) *reinterpret_cast<float4*>(B1 + ZROW * L::RB + (k << 4)) = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int k = tid; k < L::NZ * L::CPR; k += nthr) {  // the zero rows (above every staged row)
+    *reinterpret_cast<float4*>(B0 + ZBASE * L::RB + (k << 4)) = make_float4(0.f, 0.f, 0.f, 0.f);
+    if constexpr (!SB) *reinterpret_cast<float4*>(B1 + ZBASE * L::RB + (k << 4)) = make_float4(0.f, 0.f, 0.f, 0.f);
   }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
@@ -357,7 +367,8 @@ __global__ __launch_bounds__(NTB) void hv_rows_kernel(HVArgs<T> a) {
   __syncthreads();
 
   // proton-neutron part
-  const uint32_t zj = (uint32_t)ZROW;  // padding jump: operator 0, row Z
+  // padding jump: operator 0, the zero row in the lane's preferred part of the bank window
+  const uint32_t zj = (uint32_t)(ZBASE + (bank_pref(tid) & (L::NZ - 1)));
   const int dcls = 2 * a.tjmax;        // class of no change of M and parity
   uint32_t er[MP][NR];
   int eb[MP], ec[MP];

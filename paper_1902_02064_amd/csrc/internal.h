@@ -184,6 +184,7 @@ struct Model {
   std::vector<int> h_off_host, h_ncol_host;
   std::vector<int> src_blk_host;        // per (block, class): source block or -1
   std::vector<int> sec_slice0[2];       // per species sector: first sliced-ELL slice
+  std::vector<int> nlane_pos;           // per neutron SD: its lane position in its sector
   // one species empty and the other's sector too wide for the LDS-staged kernels: the
   // identical-particle part is generated per element from the two-body terms (fly.hip)
   bool fly = false;

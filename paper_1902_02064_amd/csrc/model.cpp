@@ -50,6 +50,8 @@ double clebsch(int tj1, int tm1, int tj2, int tm2, int tJ, int tM) {
 
 // ------------------------------------------------------------------ basis
 static int popc(uint64_t x) { return __builtin_popcountll(x); }
+// the four low bits of x in reverse order
+static int bitrev4(int x) { return ((x & 1) << 3) | ((x & 2) << 1) | ((x & 4) >> 1) | ((x & 8) >> 3); }
 
 // Jordan-Wigner sign of an operator on state s of one species: (-1)^(occupied below s).
 static int below_sign(uint64_t w, int s) {
@@ -484,6 +486,9 @@ void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const
         });
       }
       m.dt.nlane.upload(lane_sd);
+      m.nlane_pos.assign(S.words.size(), 0);
+      for (const auto& sec : S.sectors)
+        for (int r = 0; r < sec.size; r++) m.nlane_pos[sec.start + lane_sd[sec.start + r]] = r;
     }
     // sliced-ELL copy for the H.V kernels: slices of 64 consecutive lanes of one sector (one
     // wavefront of targets, in the lane order above), padded to the longest row of the slice,
@@ -507,10 +512,19 @@ void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const
           eval.resize(base + (size_t)w * 64, 0.0);
           for (int r = r0; r < std::min(sec.size, r0 + 64); r++) {
             const int g = sec.start + lane_sd[sec.start + r];
-            for (int k = ptr[g]; k < ptr[g + 1]; k++) {
-              const size_t at = base + (size_t)(k - ptr[g]) * 64 + (r - r0);
-              ecol[at] = col[k];
-              eval[at] = val[k];
+            // neutron rows in the bank order of the pn jump lists (the rows kernel gathers them
+            // from the staged own row the same way)
+            std::vector<int> ord(ptr[g + 1] - ptr[g]);
+            for (size_t k = 0; k < ord.size(); k++) ord[k] = ptr[g] + (int)k;
+            if (s == 1) {
+              const int pref = bitrev4(r & 15);
+              std::stable_sort(ord.begin(), ord.end(),
+                               [&](int u, int v) { return bitrev4((col[u] ^ pref) & 15) < bitrev4((col[v] ^ pref) & 15); });
+            }
+            for (size_t k = 0; k < ord.size(); k++) {
+              const size_t at = base + k * 64 + (r - r0);
+              ecol[at] = col[ord[k]];
+              eval[at] = val[ord[k]];
             }
           }
         }
@@ -617,9 +631,19 @@ void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const
         }
       }
       const int own = (int)(g - S.sectors[S.sector_of[g]].start);
+      // Neutron lists in bank order: the rows kernel reads source row n from LDS at n times the
+      // tile row size, so the source's low bits choose the part of a 256-byte bank window the
+      // row lies in (2 parts for 128-byte rows, 4 for 64-byte rows, ...). The lane at position
+      // l of its sector prefers sources whose low four bits match bitrev4(l mod 16) (the lowest
+      // bit most), so that at each step the lanes of a wavefront spread over the window for
+      // every tile size at once; the kernel reads source chunks in lane-rotated order within
+      // the row, which covers the rest of the window.
+      const int pref = s == 1 ? bitrev4(m.nlane_pos[g] & 15) : 0;
+      auto bank_key = [&](int src) { return bitrev4((src ^ pref) & 15); };
       for (auto& b : bucket)
         std::stable_sort(b.begin(), b.end(), [&](auto& u, auto& v) {
           if (s == 1 && (u.first == own) != (v.first == own)) return u.first == own;
+          if (s == 1 && bank_key(u.first) != bank_key(v.first)) return bank_key(u.first) < bank_key(v.first);
           return u.first < v.first;
         });
     }
