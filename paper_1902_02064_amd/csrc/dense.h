@@ -21,9 +21,10 @@ struct Scratch {
 template <class TA, class TB>
 void tn(const TA* A, int64_t lda, int m, const TB* B, int64_t ldb, int nb, int64_t D, double* C, Scratch& s,
         hipStream_t st);
-// Bout = Bin - A C; mode 1 also forms A^T Bout into Pout, mode 2 keeps Bout^T Bout partials in s.
-template <class TA, class TI>
-void update(const TA* A, int64_t lda, int m, const double* C, const TI* Bin, int64_t ldi, double* Bout, int64_t ldo,
+// Bout = Bin - A C; mode 1 also forms A^T Bout into Pout, mode 2 keeps Bout^T Bout partials in s
+// (of the stored values; FP32 Bout: modes 0 and 2 only).
+template <class TA, class TI, class TO = double>
+void update(const TA* A, int64_t lda, int m, const double* C, const TI* Bin, int64_t ldi, TO* Bout, int64_t ldo,
             int nb, int64_t D, int mode, double* Pout, Scratch& s, hipStream_t st);
 // Bout = Bin R (R nb x nb); gram keeps Bout^T Bout partials in s.
 template <class TI, class TO>

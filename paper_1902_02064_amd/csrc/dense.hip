@@ -158,10 +158,12 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __re
 // (Bin == nullptr: Bout = A C.)
 // mode 0: update only; mode 1: also part[g] += A^T Bout (m x nb); mode 2: also part[g] += Bout^T Bout (nb x nb).
 // C (m x nb, FP64) is staged in LDS, padded to 16-multiples with zeros.
-template <class TA, class TI, int WAVES, int MAXI, int MAXC>
+// Bout may be FP32 (the mixed-precision block kept in the basis array): the fused products then
+// use the stored (rounded) values.
+template <class TA, class TI, class TO, int WAVES, int MAXI, int MAXC>
 __global__ __launch_bounds__(WAVES * 64) void update_kernel(const TA* __restrict__ A, int64_t lda, int m,
                                                      const double* __restrict__ C, const TI* Bin, int64_t ldi,
-                                                     double* Bout, int64_t ldo, int nb, int64_t D, int mode,
+                                                     TO* Bout, int64_t ldo, int nb, int64_t D, int mode,
                                                      double* __restrict__ part) {
   constexpr int ROWS = WAVES * 16;
   extern __shared__ double lds[];
@@ -215,8 +217,9 @@ __global__ __launch_bounds__(WAVES * 64) void update_kernel(const TA* __restrict
         const int c = q * 16 + li;
         double val = 0.0;
         if (r < D && c < nb) {
-          val = Bin ? ld(Bin + r * ldi + c) - acc[q][v] : acc[q][v];
-          Bout[r * ldo + c] = val;
+          const TO out = (TO)(Bin ? ld(Bin + r * ldi + c) - acc[q][v] : acc[q][v]);
+          Bout[r * ldo + c] = out;
+          val = (double)out;
         }
         Wt[rl * nbp + c] = val;
       }
@@ -457,9 +460,10 @@ __global__ __launch_bounds__(256) void apply_small_kernel(const TI* Bin, int64_t
       const double* tr = tile + rl * nb;
       double s = 0.0;
       for (int k = 0; k < nb; k++) s += tr[k] * Rs[k * nb + c];
-      outt[e] = s;
+      const TO so = (TO)s;  // the Gram partial is that of the stored (possibly rounded) values
+      outt[e] = (double)so;
       const int64_t r = r0 + rl;
-      if (r < D) Bout[r * ldo + c] = (TO)s;
+      if (r < D) Bout[r * ldo + c] = so;
     }
     if (gram) {
       __syncthreads();
@@ -775,11 +779,12 @@ void tn(const TA* A, int64_t lda, int m, const TB* B, int64_t ldb, int nb, int64
   TRBL_HIP(hipGetLastError());
 }
 
-template <class TA, class TI>
-void update(const TA* A, int64_t lda, int m, const double* C, const TI* Bin, int64_t ldi, double* Bout, int64_t ldo,
+template <class TA, class TI, class TO>
+void update(const TA* A, int64_t lda, int m, const double* C, const TI* Bin, int64_t ldi, TO* Bout, int64_t ldo,
             int nb, int64_t D, int mode, double* Pout, Scratch& s, hipStream_t st) {
   TRBL_REQUIRE(m >= 1 && m <= 768 && nb >= 1 && nb <= 64, TRBL_E_INVALID, "projection shape out of range");
   const int mt = (m + 15) / 16, ct = (nb + 15) / 16, npan = (m + 63) / 64;
+  if constexpr (sizeof(TO) == 8) {
   if (mode == 1 && mt <= 32 && ct == 1 && Bin) {  // one pass over A for the update and the projection
     const size_t shmf = (size_t)(16 * (mt * 16 + 4) + 16 * 16 * 16 + 16 * 16) * sizeof(double);
     const int G = grid_for(D, 16, 256);  // one resident workgroup of 16 waves per CU
@@ -796,6 +801,7 @@ void update(const TA* A, int64_t lda, int m, const double* C, const TI* Bin, int
     TRBL_HIP(hipGetLastError());
     return;
   }
+  }
   auto shm_for = [&](int waves) {
     size_t b = (size_t)(mt * 16 * ct * 16 + waves * 16 * ct * 16) * sizeof(double);
     return std::max(b, (size_t)ct * 16 * ct * 16 * sizeof(double));
@@ -808,7 +814,7 @@ void update(const TA* A, int64_t lda, int m, const double* C, const TI* Bin, int
   double* part = mode ? s.partials((size_t)G * plen) : nullptr;
   const int mi = (npan + waves - 1) / waves;  // 64-column panels per wave (mode 1)
 #define UPD_LAUNCH(W, MI, MC)                                                                                     \
-  hipLaunchKernelGGL((update_kernel<TA, TI, W, MI, MC>), dim3(G), dim3(W * 64), shm, st, A, lda, m, C, Bin, ldi, \
+  hipLaunchKernelGGL((update_kernel<TA, TI, TO, W, MI, MC>), dim3(G), dim3(W * 64), shm, st, A, lda, m, C, Bin, ldi, \
                      Bout, ldo, nb, D, mode, part)
   if (waves == 8) {
     if (ct == 1) {
@@ -839,8 +845,9 @@ void update(const TA* A, int64_t lda, int m, const double* C, const TI* Bin, int
 template <class TI, class TO>
 void apply_small(const TI* Bin, int64_t ldi, const double* R, TO* Bout, int64_t ldo, int nb, int64_t D, bool gram,
                  Scratch& s, hipStream_t st) {
-  if constexpr (sizeof(TO) == 8) {  // FP64 output: the MFMA row-streaming kernel, Bout = Bin R (+ Gram)
-    update<TI, TI>(Bin, ldi, nb, R, nullptr, 0, Bout, ldo, nb, D, gram ? 2 : 0, nullptr, s, st);
+  if constexpr (sizeof(TO) == 8 || sizeof(TI) == sizeof(TO)) {
+    // FP64 output, or FP32 in and out: the MFMA row-streaming kernel, Bout = Bin R (+ Gram)
+    update<TI, TI, TO>(Bin, ldi, nb, R, nullptr, 0, Bout, ldo, nb, D, gram ? 2 : 0, nullptr, s, st);
     return;
   }
   const int rows = 2048 / nb;
@@ -976,16 +983,20 @@ template void tn<float, double>(const float*, int64_t, int, const double*, int64
                                 hipStream_t);
 template void tn<double, float>(const double*, int64_t, int, const float*, int64_t, int, int64_t, double*, Scratch&,
                                 hipStream_t);
-template void update<double, double>(const double*, int64_t, int, const double*, const double*, int64_t, double*,
-                                     int64_t, int, int64_t, int, double*, Scratch&, hipStream_t);
-template void update<float, float>(const float*, int64_t, int, const double*, const float*, int64_t, double*, int64_t,
-                                   int, int64_t, int, double*, Scratch&, hipStream_t);
-template void update<float, double>(const float*, int64_t, int, const double*, const double*, int64_t, double*,
-                                    int64_t, int, int64_t, int, double*, Scratch&, hipStream_t);
+template void update<double, double, double>(const double*, int64_t, int, const double*, const double*, int64_t,
+                                             double*, int64_t, int, int64_t, int, double*, Scratch&, hipStream_t);
+template void update<float, float, double>(const float*, int64_t, int, const double*, const float*, int64_t, double*,
+                                           int64_t, int, int64_t, int, double*, Scratch&, hipStream_t);
+template void update<float, double, double>(const float*, int64_t, int, const double*, const double*, int64_t,
+                                            double*, int64_t, int, int64_t, int, double*, Scratch&, hipStream_t);
+template void update<float, float, float>(const float*, int64_t, int, const double*, const float*, int64_t, float*,
+                                          int64_t, int, int64_t, int, double*, Scratch&, hipStream_t);
 template void apply_small<double, double>(const double*, int64_t, const double*, double*, int64_t, int, int64_t, bool,
                                           Scratch&, hipStream_t);
 template void apply_small<double, float>(const double*, int64_t, const double*, float*, int64_t, int, int64_t, bool,
                                          Scratch&, hipStream_t);
+template void apply_small<float, float>(const float*, int64_t, const double*, float*, int64_t, int, int64_t, bool,
+                                        Scratch&, hipStream_t);
 template void apply_small<float, double>(const float*, int64_t, const double*, double*, int64_t, int, int64_t, bool,
                                          Scratch&, hipStream_t);
 template void rowgemm<double, double>(const double*, int64_t, int, const double*, int64_t, int, double*, int64_t,

@@ -13,9 +13,10 @@
 // block would exceed l_m stored vectors:
 //   v_k := sum_j v_j U_jk (k <= l_s),  V_1 := V_{k+1},  r := beta_k U[last block, 1:l_s],
 //   T := [diag(theta_1..l_s) r^T ; r .],  k_x := l_s.
-// Mixed precision: the stored vectors Q and H.V are FP32; projections, the
-// orthogonalised W, QR, T and its eigenproblem are FP64; at the end an FP64
-// Rayleigh-Ritz step on the Ritz vectors refines the eigenvalues.
+// Mixed precision: the stored vectors Q and H.V are FP32, and W is kept in the basis
+// array's next block (FP32 storage; every projection, update, Gram matrix and the
+// QR factors are computed in FP64); T and its eigenproblem are FP64; at the end an
+// FP64 Rayleigh-Ritz step on the Ritz vectors refines the eigenvalues.
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -74,11 +75,18 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
 
   const int64_t ldq = round4(lm);
   const int ldu = std::max(ls, neig);
-  DevBuf Qb, Vkb, Wb, W32b, Tb, C1b, C2b, Rb, thb, Ub, rhob, stb;
+  DevBuf Qb, Vkb, Wb, Tb, C1b, C2b, Rb, thb, Ub, rhob, stb;
   Qb.alloc((size_t)D * ldq * sizeof(TQ));
   Vkb.alloc((size_t)D * nb * sizeof(TQ));
-  Wb.alloc((size_t)D * nb * sizeof(double));
-  if (mixed) W32b.alloc((size_t)D * nb * sizeof(float));
+  // FP64: the new block W is an FP64 work array. Mixed precision: H V_k lands in the basis
+  // array's next column block (FP32), and the projections, the QR and the normalised block stay
+  // there, so the basis can keep the memory of the FP64 block; an FP64 copy is made only on the
+  // rare breakdown path.
+  if (!mixed) Wb.alloc((size_t)D * nb * sizeof(double));
+  auto w64 = [&]() {
+    Wb.alloc((size_t)D * nb * sizeof(double));
+    return Wb.as<double>();
+  };
   Tb.alloc((size_t)lm * lm * sizeof(double));
   C1b.alloc((size_t)lm * nb * sizeof(double));
   C2b.alloc((size_t)lm * nb * sizeof(double));
@@ -89,8 +97,7 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
   stb.alloc(4 * sizeof(int));
   TQ* Q = Qb.as<TQ>();
   TQ* Vk = Vkb.as<TQ>();  // packed copy of the current block: H.V stages whole source rows
-  double* W = Wb.as<double>();
-  float* W32 = W32b.as<float>();
+  double* W = Wb.as<double>();  // FP64 only (mixed: w64() on demand)
   double* T = Tb.as<double>();
   double* C1 = C1b.as<double>();
   double* C2 = C2b.as<double>();
@@ -187,14 +194,21 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
   mask_rows<TQ>(Q, ldq, D, nb, o.mask, st);
   tn<TQ, TQ>(Q, ldq, nb, Q, ldq, nb, D, C1, sc, st);
   chol(C1, 1, nb, R1, R1i, nullptr, nullptr, status, st);
-  apply_small<TQ, double>(Q, ldq, R1i, W, nb, nb, D, true, sc, st);
-  chol(sc.last_part, sc.last_G, nb, R2, R2i, nullptr, nullptr, status + 1, st);
-  apply_small<double, TQ>(W, nb, R2i, Q, ldq, nb, D, false, sc, st);
+  if (mixed) {
+    apply_small<TQ, TQ>(Q, ldq, R1i, Q, ldq, nb, D, true, sc, st);
+    chol(sc.last_part, sc.last_G, nb, R2, R2i, nullptr, nullptr, status + 1, st);
+    apply_small<TQ, TQ>(Q, ldq, R2i, Q, ldq, nb, D, false, sc, st);
+  } else {
+    apply_small<TQ, double>(Q, ldq, R1i, W, nb, nb, D, true, sc, st);
+    chol(sc.last_part, sc.last_G, nb, R2, R2i, nullptr, nullptr, status + 1, st);
+    apply_small<double, TQ>(W, nb, R2i, Q, ldq, nb, D, false, sc, st);
+  }
   TRBL_HIP(hipMemsetAsync(T, 0, sizeof(double) * (size_t)lm * lm, st));
   int sth[4] = {0, 0, 0, 0};
   TRBL_HIP(hipMemcpyAsync(sth, status, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
   TRBL_HIP(hipStreamSynchronize(st));
   if (sth[0] || sth[1]) {  // rank-deficient start block: column-wise QR with replacement
+    W = w64();
     if (o.v0) copy_cols<TQ, double>(static_cast<const TQ*>(o.v0), nb, W, nb, D, nb, st);
     else {
       random_block<TQ>(Q, ldq, D, nb, o.seed, st);
@@ -219,11 +233,15 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
     mcur = c0 + nb;
     copy_cols<TQ, TQ>(Q + c0, ldq, Vk, nb, D, nb, st);
     TRBL_HIP(hipEventRecord(ev.e[0], st));
-    // W := H V_k
-    void* Wh = mixed ? (void*)W32 : (void*)W;
-    apply_h(mixed ? TRBL_MIXED : TRBL_FP64, nb, Vk, nb, Wh, nb);
-    if (mixed) mask_rows<float>(W32, nb, D, nb, o.mask, st);
-    else mask_rows<double>(W, nb, D, nb, o.mask, st);
+    // W := H V_k (mixed: in the basis array's next block, Wq)
+    float* Wq = mixed ? reinterpret_cast<float*>(Q) + mcur : nullptr;
+    if (mixed) {
+      apply_h(TRBL_MIXED, nb, Vk, nb, Wq, ldq);
+      mask_rows<float>(Wq, ldq, D, nb, o.mask, st);
+    } else {
+      apply_h(TRBL_FP64, nb, Vk, nb, W, nb);
+      mask_rows<double>(W, nb, D, nb, o.mask, st);
+    }
     TRBL_HIP(hipEventRecord(ev.e[1], st));
     // alpha_k = V_k^T W, then block classical Gram-Schmidt twice against all stored vectors.
     // The first pass takes its coefficients from T: in exact arithmetic Q^T H V_k is the
@@ -232,13 +250,13 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
     // order of the rounding of a computed first pass, and the full second pass removes it.
     const int r_lo = k == 1 ? 0 : c0 - nb;
     if (mixed) {
-      tn<float, float>((const float*)Q + c0, ldq, nb, W32, nb, nb, D, C1 + (size_t)c0 * nb, sc, st);
+      tn<float, float>((const float*)Q + c0, ldq, nb, Wq, ldq, nb, D, C1 + (size_t)c0 * nb, sc, st);
       t_alpha(T, lm, c0, nb, C1, st);
       t_column(T, lm, c0, r_lo, nb, C1, st);
-      update<float, float>((const float*)Q + r_lo, ldq, mcur - r_lo, C1 + (size_t)r_lo * nb, W32, nb, W, nb, nb, D,
-                           0, nullptr, sc, st);
-      tn<float, double>((const float*)Q, ldq, mcur, W, nb, nb, D, C2, sc, st);
-      update<float, double>((const float*)Q, ldq, mcur, C2, W, nb, W, nb, nb, D, 2, nullptr, sc, st);
+      update<float, float, float>((const float*)Q + r_lo, ldq, mcur - r_lo, C1 + (size_t)r_lo * nb, Wq, ldq, Wq,
+                                  ldq, nb, D, 0, nullptr, sc, st);
+      tn<float, float>((const float*)Q, ldq, mcur, Wq, ldq, nb, D, C2, sc, st);
+      update<float, float, float>((const float*)Q, ldq, mcur, C2, Wq, ldq, Wq, ldq, nb, D, 2, nullptr, sc, st);
     } else {
       tn<double, double>((const double*)Q + c0, ldq, nb, W, nb, nb, D, C1 + (size_t)c0 * nb, sc, st);
       t_alpha(T, lm, c0, nb, C1, st);
@@ -251,23 +269,31 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
     TRBL_HIP(hipEventRecord(ev.e[2], st));
     // V_{k+1} beta_k := QR(W): Cholesky QR twice
     chol(sc.last_part, sc.last_G, nb, R1, R1i, nullptr, nullptr, status, st);
-    apply_small<double, double>(W, nb, R1i, W, nb, nb, D, true, sc, st);
-    chol(sc.last_part, sc.last_G, nb, R2, R2i, R1, beta, status + 1, st);
-    apply_small<double, TQ>(W, nb, R2i, Q + mcur, ldq, nb, D, false, sc, st);
+    if (mixed) {
+      apply_small<float, float>(Wq, ldq, R1i, Wq, ldq, nb, D, true, sc, st);
+      chol(sc.last_part, sc.last_G, nb, R2, R2i, R1, beta, status + 1, st);
+      apply_small<float, float>(Wq, ldq, R2i, Wq, ldq, nb, D, false, sc, st);
+    } else {
+      apply_small<double, double>(W, nb, R1i, W, nb, nb, D, true, sc, st);
+      chol(sc.last_part, sc.last_G, nb, R2, R2i, R1, beta, status + 1, st);
+      apply_small<double, TQ>(W, nb, R2i, Q + mcur, ldq, nb, D, false, sc, st);
+    }
     t_beta(T, lm, c0, mcur, nb, beta, st);
     TRBL_HIP(hipMemcpyAsync(sth, status, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
     TRBL_HIP(hipStreamSynchronize(st));
     if (sth[0] || sth[1]) {
       // breakdown: W was scaled in place; form it again (same arithmetic) and take the
       // column-wise QR with replacement
-      apply_h(mixed ? TRBL_MIXED : TRBL_FP64, nb, Vk, nb, Wh, nb);
-      if (mixed) mask_rows<float>(W32, nb, D, nb, o.mask, st);
-      else mask_rows<double>(W, nb, D, nb, o.mask, st);
       if (mixed) {
-        tn<float, float>((const float*)Q, ldq, mcur, W32, nb, nb, D, C1, sc, st);
-        update<float, float>((const float*)Q, ldq, mcur, C1, W32, nb, W, nb, nb, D, 1, C2, sc, st);
+        W = w64();
+        apply_h(TRBL_MIXED, nb, Vk, nb, Wq, ldq);
+        mask_rows<float>(Wq, ldq, D, nb, o.mask, st);
+        tn<float, float>((const float*)Q, ldq, mcur, Wq, ldq, nb, D, C1, sc, st);
+        update<float, float>((const float*)Q, ldq, mcur, C1, Wq, ldq, W, nb, nb, D, 1, C2, sc, st);
         update<float, double>((const float*)Q, ldq, mcur, C2, W, nb, W, nb, nb, D, 0, nullptr, sc, st);
       } else {
+        apply_h(TRBL_FP64, nb, Vk, nb, W, nb);
+        mask_rows<double>(W, nb, D, nb, o.mask, st);
         tn<double, double>((const double*)Q, ldq, mcur, W, nb, nb, D, C1, sc, st);
         update<double, double>((const double*)Q, ldq, mcur, C1, W, nb, W, nb, nb, D, 1, C2, sc, st);
         update<double, double>((const double*)Q, ldq, mcur, C2, W, nb, W, nb, nb, D, 0, nullptr, sc, st);
@@ -345,9 +371,9 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
     }
     if (restart_next && it < o.max_iter) {
       TRBL_HIP(hipEventRecord(ev.e[4], st));
-      // W is free between iterations: the work buffer of restarts that keep more than 208 vectors
-      rowgemm<TQ, TQ>(Q, ldq, mcur, U, ldu, ls, Q, ldq, D, mcur, ls, nb, st, reinterpret_cast<TQ*>(W),
-                      D * nb * (int64_t)(sizeof(double) / sizeof(TQ)));
+      // the packed block is free between iterations: the work buffer of restarts that keep more
+      // than 208 vectors
+      rowgemm<TQ, TQ>(Q, ldq, mcur, U, ldu, ls, Q, ldq, D, mcur, ls, nb, st, Vk, D * nb);
       t_restart(T, lm, lm, theta, ls, beta, nb, U, ldu, mcur, st);
       if (corrupt_restart && restarts == 0 && ls >= 2)  // testing aid: damage a kept Ritz vector
         copy_cols<TQ, TQ>(Q + 1, ldq, Q, ldq, D / 2, 1, st);
@@ -375,8 +401,14 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
     // pair, nb columns at a time (the W block holds H X, the packed block or a new one holds X
     // where the caller wants no vectors). rho from T equals it in exact arithmetic; a damaged
     // basis (which T cannot see) shows up here.
-    const int w = nb;
-    DevBuf Xown;
+    // (mixed precision keeps no FP64 block during the iteration: an FP64 one of at most 8 GB here)
+    const int w = mixed ? (int)std::max<int64_t>(1, std::min<int64_t>(nb, (int64_t)(8e9 / (16.0 * D)))) : nb;
+    DevBuf Xown, Wfin;
+    double* Wr = W;
+    if (mixed) {
+      Wfin.alloc((size_t)D * w * sizeof(double));
+      Wr = Wfin.as<double>();
+    }
     double* Xc = nullptr;
     if (!evecs) {
       if (sizeof(TQ) == 8) Xc = reinterpret_cast<double*>(Vk);
@@ -401,11 +433,11 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
         X = Xc;
         ldx = cw;
       }
-      apply_h(TRBL_FP64, cw, X, ldx, W, cw);
-      mask_rows<double>(W, cw, D, cw, o.mask, st);
-      resid_cols(W, cw, X, ldx, theta + c, cw, D, rs.as<double>() + c, sc, st);
+      apply_h(TRBL_FP64, cw, X, ldx, Wr, cw);
+      mask_rows<double>(Wr, cw, D, cw, o.mask, st);
+      resid_cols(Wr, cw, X, ldx, theta + c, cw, D, rs.as<double>() + c, sc, st);
       double* part = sc.partials((size_t)dot_cols_parts(D) * cw);
-      dot_cols(W, cw, X, ldx, cw, D, part, xhx + c, st);
+      dot_cols(Wr, cw, X, ldx, cw, D, part, xhx + c, st);
       dot_cols(X, ldx, X, ldx, cw, D, part, xx + c, st);
     }
     std::vector<double> tr(3 * (size_t)nv);
@@ -429,8 +461,7 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
   } else {
     // FP64 Rayleigh-Ritz on span(X), X = Q U[:, :n_eig] stored in place in Q's first n_eig columns
     TRBL_HIP(hipEventRecord(ev.e[0], st));
-    rowgemm<TQ, TQ>(Q, ldq, mcur, U, ldu, neig, Q, ldq, D, -1, 0, 0, st, reinterpret_cast<TQ*>(W),
-                    D * nb * (int64_t)(sizeof(double) / sizeof(TQ)));
+    rowgemm<TQ, TQ>(Q, ldq, mcur, U, ldu, neig, Q, ldq, D, -1, 0, 0, st, Vk, D * nb);
     const int cw = (int)std::max<int64_t>(1, std::min<int64_t>(32, (int64_t)(8e9 / (16.0 * D))));
     DevBuf Xc, Hc, Sb, Gb, Mb, Lb, Yb, Yp, tmp, th2, st2;
     Xc.alloc((size_t)D * cw * sizeof(double));
