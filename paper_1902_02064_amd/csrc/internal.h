@@ -110,7 +110,7 @@ struct DeviceTables {
   DevBuf pwords, nwords, ppart, npart, psec_start, psec_size, nsec_start, nsec_size, blk_of_sec;
   DevBuf psec_tm, psec_par, nsec_tm, nsec_par;
   // jumps
-  DevBuf pj_start, pj_idx, pj_meta, nj_start, nj_idx, nj_meta, pj_pack, nj_pack;  // nj_* class-major
+  DevBuf pj_start, pj_idx, pj_meta, nj_start, nj_idx, nj_meta, nj_pack;  // nj_* class-major
   DevBuf pg_start, pg_desc;  // per proton SD: jump groups (class, first, end, source row) as int4
   DevBuf pg_cend;            // per jump group: first group after the run of its class
   DevBuf nj32;               // neutron jumps, class-major, packed: sign << 31 | op << 16 | source
@@ -207,6 +207,26 @@ double clebsch(int tj1, int tm1, int tj2, int tm2, int tJ, int tM);
 // device launchers (hv.hip)
 void launch_apply(const Model& m, int precision, int nb, const void* V, int64_t ldv, void* W, int64_t ldw,
                   hipStream_t s);
+// One-body jump lists of one species, generated on the device (jumps.hip): counts per
+// (determinant, class) [g * ncl + c], the lists written at given starts and sorted, the proton
+// jump groups, and the packed neutron forms.
+class JumpTables {
+ public:
+  JumpTables(const Model& m, int s);
+  void set_ops(const std::vector<int>& ocls, const std::vector<int>& oidx);
+  std::vector<int> counts();
+  void fill(const std::vector<int>& start_gc, int64_t total, const std::vector<int>& pref, DevBuf& jidx,
+            DevBuf& jmeta);
+  std::vector<int> group_counts(const DevBuf& start, const DevBuf& jidx);
+  void group_fill(const DevBuf& start, const DevBuf& jidx, const DevBuf& gstart, int ngroups, DevBuf& gdesc,
+                  DevBuf& cend);
+  void pack(const DevBuf& jidx, const DevBuf& jmeta, int64_t n, DevBuf& pack, DevBuf& p32);
+
+ private:
+  const Model& m_;
+  int s_, ns_ = 0, ncl_ = 0, nsd_ = 0;
+  DevBuf ocls_, oidx_;
+};
 void launch_rank(const Model& m, const uint64_t* pb, const uint64_t* nb, int64_t n, int64_t* idx, hipStream_t s);
 // build the block-product plans of the given column counts now (device tables of the work
 // decomposition), so that later products of those widths allocate nothing

@@ -388,6 +388,30 @@ void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const
     m.has_h = true;
     return;
   }
+  // one-body operators c+_y c_x of each class (change of 2M and parity), numbered inside the
+  // class; the same numbering for both species
+  const Classes& cl = m.cl;
+  const int ncl = cl.nclass;
+  std::vector<std::vector<std::pair<int, int>>> pops(ncl);
+  std::vector<int> op_idx(ns * ns), op_cls(ns * ns);
+  for (int x = 0; x < ns; x++)
+    for (int y = 0; y < ns; y++) {
+      // jump from a determinant that removes x and adds y: its 2M changes by tm[y] - tm[x]
+      const int d2 = m.st_tm[y] - m.st_tm[x];
+      const int flip = (m.orbits[m.st_orb[x]].l + m.orbits[m.st_orb[y]].l) & 1;
+      const int c = cl.cls(d2, flip);
+      op_cls[x * ns + y] = c;
+      op_idx[x * ns + y] = (int)pops[c].size();
+      pops[c].push_back({x, y});
+    }
+  // the one-body jumps of each species are generated on the device; their counts per
+  // (determinant, class) come first (the neutron lane order below needs them)
+  JumpTables jt[2] = {JumpTables(m, 0), JumpTables(m, 1)};
+  std::vector<int> jcount[2];
+  for (int s = 0; s < 2; s++) {
+    jt[s].set_ops(op_cls, op_idx);
+    jcount[s] = jt[s].counts();
+  }
   for (int s = 0; s < 2; s++) {
     const Species& S = m.sp[s];
     const std::vector<MTerm>& T = s == 0 ? m.terms_pp : m.terms_nn;
@@ -457,20 +481,7 @@ void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const
     for (size_t g = 0; g < S.words.size(); g++) lane_sd[g] = (int)(g - S.sectors[S.sector_of[g]].start);
     if (s == 1) {
       const int nc = m.cl.nclass;
-      std::vector<int> cnt(S.words.size() * (size_t)nc, 0);
-      for (size_t g = 0; g < S.words.size(); g++) {
-        const uint64_t w = S.words[g];
-        for (uint64_t xx = w; xx; xx &= xx - 1) {
-          const int x = __builtin_ctzll(xx);
-          const uint64_t r0 = w & ~(1ull << x);
-          for (int y = 0; y < ns; y++) {
-            if (r0 & (1ull << y)) continue;
-            if (S.index.find(r0 | (1ull << y)) == S.index.end()) continue;
-            const int flip = (m.orbits[m.st_orb[x]].l + m.orbits[m.st_orb[y]].l) & 1;
-            cnt[g * nc + m.cl.cls(m.st_tm[y] - m.st_tm[x], flip)]++;
-          }
-        }
-      }
+      const std::vector<int>& cnt = jcount[1];
       std::vector<int> corder;  // classes by |change of 2M|, the unchanged class first
       for (int di = 0; di <= m.cl.tjmax * 2; di += 2)  // changes of 2M are even
         for (int f = 0; f < 2; f++)
@@ -557,38 +568,20 @@ void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const
   }
 
   // ---------------- one-body jumps and the pn coefficient table (App. B, second part)
-  const Classes& cl = m.cl;
-  const int ncl = cl.nclass;
-  // op numbering inside each class, separately for the proton side (a,c) and neutron side (b,d)
-  std::vector<std::vector<std::pair<int, int>>> pops(ncl), nops(ncl);
-  std::vector<int> pop_idx(ns * ns), nop_idx(ns * ns), pop_cls(ns * ns), nop_cls(ns * ns);
-  for (int x = 0; x < ns; x++)
-    for (int y = 0; y < ns; y++) {
-      // proton op c+_x c_y: jump from target removes x, adds y; source 2M changes by tm[y]-tm[x]
-      int d2 = m.st_tm[y] - m.st_tm[x];
-      int flip = (m.orbits[m.st_orb[x]].l + m.orbits[m.st_orb[y]].l) & 1;
-      int c = cl.cls(d2, flip);
-      pop_cls[x * ns + y] = c;
-      pop_idx[x * ns + y] = (int)pops[c].size();
-      pops[c].push_back({x, y});
-      nop_cls[x * ns + y] = c;
-      nop_idx[x * ns + y] = (int)nops[c].size();
-      nops[c].push_back({x, y});
-    }
   // table h[cls][op_p][op_n] over proton class cls and neutron class conj(cls)
   std::vector<int> hoff(ncl + 1, 0), hncol(ncl, 0);
   for (int c = 0; c < ncl; c++) {
-    hncol[c] = (int)nops[cl.conj(c)].size();
+    hncol[c] = (int)pops[cl.conj(c)].size();
     hoff[c + 1] = hoff[c] + (int)pops[c].size() * hncol[c];
   }
   std::vector<double> h(hoff[ncl], 0.0);
   std::vector<int> hterm(hoff[ncl], -1);
   for (int k = 0; k < (int)m.terms_pn.size(); k++) {
     const MTerm& t = m.terms_pn[k];  // c+_a(p) c+_b(n) c_d(n) c_c(p): proton op (a,c), neutron op (b,d)
-    int c = pop_cls[t.a * ns + t.c];
-    int cn = nop_cls[t.b * ns + t.d];
+    const int c = op_cls[t.a * ns + t.c];
+    const int cn = op_cls[t.b * ns + t.d];
     TRBL_REQUIRE(cn == cl.conj(c), TRBL_E_INVALID, "pn term breaks M or parity conservation");
-    int at = hoff[c] + pop_idx[t.a * ns + t.c] * hncol[c] + nop_idx[t.b * ns + t.d];
+    const int at = hoff[c] + op_idx[t.a * ns + t.c] * hncol[c] + op_idx[t.b * ns + t.d];
     h[at] += t.h;
     hterm[at] = k;
   }
@@ -601,132 +594,83 @@ void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const
   m.dt.h64.upload(h);
   m.dt.h32.upload(h32);
   m.dt.h_term.upload(hterm);
-  // jump lists: from each SD g' remove x in g', add y not in g' \ {x} (y == x allowed).
-  // Proton side: per (SD, class), sorted by source index so equal source rows are adjacent.
-  // Neutron side: class-major, so the lists of consecutive SDs in one class are contiguous;
-  // each list has its number operators (source = the SD itself) first, then ascending sources.
+  // Jump lists (device, jumps.hip): from each SD g' remove x in g', add y not in g' \ {x}
+  // (y == x allowed). Proton side: per (SD, class), sorted by source index so equal source rows
+  // are adjacent. Neutron side: class-major, so the lists of consecutive SDs in one class are
+  // contiguous; each list has its number operators (source = the SD itself) first, then the
+  // sources in the bank order of the SD's lane in the rows kernel (the kernel reads source row
+  // n from LDS at n times the tile row size, so a source's low bits choose the part of a
+  // 256-byte bank window its row lies in; the lane at position l prefers sources whose low four
+  // bits match bitrev4(l mod 16), lowest bit first, so that at each step the lanes of a
+  // wavefront spread over the window for every tile size at once).
   for (int s = 0; s < 2; s++) {
-    const Species& S = m.sp[s];
-    const std::vector<int>& oidx = s == 0 ? pop_idx : nop_idx;
-    const std::vector<int>& ocls = s == 0 ? pop_cls : nop_cls;
-    const int64_t nsd = (int64_t)S.words.size();
-    std::vector<std::vector<std::vector<std::pair<int, int>>>> all(nsd, std::vector<std::vector<std::pair<int, int>>>(ncl));
-    for (int64_t g = 0; g < nsd; g++) {
-      auto& bucket = all[g];
-      uint64_t w = S.words[g];
-      for (uint64_t xx = w; xx; xx &= xx - 1) {
-        int x = __builtin_ctzll(xx);
-        int sg = below_sign(w, x);
-        uint64_t r0 = w & ~(1ull << x);
-        for (int y = 0; y < ns; y++) {
-          if (r0 & (1ull << y)) continue;
-          int sy = sg * below_sign(r0, y);
-          uint64_t r = r0 | (1ull << y);
-          const auto found = S.index.find(r);
-          if (found == S.index.end()) continue;  // a sector not stored (the other species is empty)
-          int gi = found->second;
-          int local = gi - S.sectors[S.sector_of[gi]].start;
-          int c = ocls[x * ns + y];
-          bucket[c].push_back({local, (oidx[x * ns + y] << 1) | (sy < 0 ? 1 : 0)});
-        }
-      }
-      const int own = (int)(g - S.sectors[S.sector_of[g]].start);
-      // Neutron lists in bank order: the rows kernel reads source row n from LDS at n times the
-      // tile row size, so the source's low bits choose the part of a 256-byte bank window the
-      // row lies in (2 parts for 128-byte rows, 4 for 64-byte rows, ...). The lane at position
-      // l of its sector prefers sources whose low four bits match bitrev4(l mod 16) (the lowest
-      // bit most), so that at each step the lanes of a wavefront spread over the window for
-      // every tile size at once; the kernel reads source chunks in lane-rotated order within
-      // the row, which covers the rest of the window.
-      const int pref = s == 1 ? bitrev4(m.nlane_pos[g] & 15) : 0;
-      auto bank_key = [&](int src) { return bitrev4((src ^ pref) & 15); };
-      for (auto& b : bucket)
-        std::stable_sort(b.begin(), b.end(), [&](auto& u, auto& v) {
-          if (s == 1 && (u.first == own) != (v.first == own)) return u.first == own;
-          if (s == 1 && bank_key(u.first) != bank_key(v.first)) return bank_key(u.first) < bank_key(v.first);
-          return u.first < v.first;
-        });
-    }
-    std::vector<int> start, jidx, jmeta;
+    const int64_t nsd = (int64_t)m.sp[s].words.size();
+    const std::vector<int>& cnt = jcount[s];
+    std::vector<int> start_gc(nsd * ncl + (s == 0 ? 1 : 0), 0);  // start of the (g, c) list, index g * ncl + c
+    std::vector<int> start;                                      // the layout the kernels read
+    int64_t total = 0;
     if (s == 0) {
-      start.assign(nsd * ncl + 1, 0);
-      for (int64_t g = 0; g < nsd; g++)
-        for (int c = 0; c < ncl; c++) {
-          start[g * ncl + c] = (int)jidx.size();
-          for (auto& pr : all[g][c]) {
-            jidx.push_back(pr.first);
-            jmeta.push_back(pr.second);
-          }
-        }
-      start[nsd * ncl] = (int)jidx.size();
+      for (int64_t q = 0; q < nsd * ncl; q++) {
+        start_gc[q] = (int)total;
+        total += cnt[q];
+      }
+      start_gc[nsd * ncl] = (int)total;
+      start = start_gc;
     } else {
       start.assign((int64_t)ncl * (nsd + 1), 0);
       for (int c = 0; c < ncl; c++) {
         for (int64_t g = 0; g < nsd; g++) {
-          start[c * (nsd + 1) + g] = (int)jidx.size();
-          for (auto& pr : all[g][c]) {
-            jidx.push_back(pr.first);
-            jmeta.push_back(pr.second);
-          }
+          start[c * (nsd + 1) + g] = (int)total;
+          start_gc[g * ncl + c] = (int)total;
+          total += cnt[g * ncl + c];
         }
-        start[c * (nsd + 1) + nsd] = (int)jidx.size();
+        start[c * (nsd + 1) + nsd] = (int)total;
       }
     }
-    std::vector<int> pack(2 * jidx.size());
-    for (size_t q = 0; q < jidx.size(); q++) {
-      pack[2 * q] = jidx[q];
-      pack[2 * q + 1] = jmeta[q];
+    TRBL_REQUIRE(total < ((int64_t)1 << 31), TRBL_E_INVALID, "too many one-body jumps");
+    std::vector<int> pref;
+    if (s == 1) {
+      pref.resize(nsd);
+      for (int64_t g = 0; g < nsd; g++) pref[g] = bitrev4(m.nlane_pos[g] & 15);
     }
+    DevBuf& jidx = s == 0 ? m.dt.pj_idx : m.dt.nj_idx;
+    DevBuf& jmeta = s == 0 ? m.dt.pj_meta : m.dt.nj_meta;
+    jt[s].fill(start_gc, total, pref, jidx, jmeta);
+    (s == 0 ? m.dt.pj_start : m.dt.nj_start).upload(start);
+    (s == 0 ? m.pj_count : m.nj_count) = (int)total;
     if (s == 1) {
       // neutron jumps packed in one word for the rows kernel: sign in bit 31, op index in
       // bits 16..30, source index inside its sector in bits 0..15
-      std::vector<uint32_t> p32(jidx.size() + 32, 0u);  // padded: register loads read up to 32 past a list
-      for (size_t q = 0; q < jidx.size(); q++) {
-        const int op = jmeta[q] >> 1;
-        TRBL_REQUIRE(jidx[q] >= 0 && jidx[q] < 65536 && op < 32768, TRBL_E_INVALID,
-                     "neutron sector or operator class too large for the packed jump lists");
-        p32[q] = ((uint32_t)(jmeta[q] & 1) << 31) | ((uint32_t)op << 16) | (uint32_t)jidx[q];
-      }
-      m.dt.nj32.upload(p32);
-      int mx = 0;
-      for (int c = 0; c < ncl; c++)
-        for (int64_t g = 0; g < nsd; g++) mx = std::max(mx, start[c * (nsd + 1) + g + 1] - start[c * (nsd + 1) + g]);
+      int maxsec = 0, maxops = 0, mx = 0;
+      for (const auto& sec : m.sp[1].sectors) maxsec = std::max(maxsec, sec.size);
+      for (const auto& v : pops) maxops = std::max(maxops, (int)v.size());
+      TRBL_REQUIRE(maxsec <= 65536 && maxops <= 32768, TRBL_E_INVALID,
+                   "neutron sector or operator class too large for the packed jump lists");
+      jt[1].pack(jidx, jmeta, total, m.dt.nj_pack, m.dt.nj32);
+      for (int x : cnt) mx = std::max(mx, x);
       m.max_nj_class = mx;
-    }
-    (s == 0 ? m.dt.pj_start : m.dt.nj_start).upload(start);
-    if (s == 0) {
-      // proton jump groups of every SD: runs of jumps of one class with one source row,
-      // class by class, as (class, first jump, end jump, source row)
-      std::vector<int> gstart(nsd + 1, 0), gdesc;
-      for (int64_t g = 0; g < nsd; g++) {
-        gstart[g] = (int)(gdesc.size() / 4);
-        for (int c = 0; c < ncl; c++)
-          for (int j = start[g * ncl + c]; j < start[g * ncl + c + 1];) {
-            int je = j + 1;
-            while (je < start[g * ncl + c + 1] && jidx[je] == jidx[j]) je++;
-            gdesc.insert(gdesc.end(), {c, j, je, jidx[j]});
-            j = je;
-          }
-      }
-      gstart[nsd] = (int)(gdesc.size() / 4);
-      // per group: the first group after the run of its class (same SD)
-      const int ng = (int)(gdesc.size() / 4);
-      std::vector<int> cend(ng + 1, ng);
-      for (int64_t g = 0; g < nsd; g++)
-        for (int q = gstart[g + 1] - 1; q >= gstart[g]; q--)
-          cend[q] = (q + 1 < gstart[g + 1] && gdesc[4 * (q + 1)] == gdesc[4 * q]) ? cend[q + 1] : q + 1;
+    } else {
+      // proton jump groups of every SD: runs of jumps of one class with one source row, class
+      // by class, as (class, first jump, end jump, source row); per group the first group after
+      // the run of its class
+      const std::vector<int> ng = jt[0].group_counts(m.dt.pj_start, jidx);
+      std::vector<int> gstart(nsd + 1, 0);
       int mg = 0;
-      for (int q = 0; q < ng; q++) mg = std::max(mg, (cend[q] - q) * hncol[gdesc[4 * q]]);
+      for (int64_t g = 0; g < nsd; g++) {
+        int t = 0;
+        for (int c = 0; c < ncl; c++) {
+          t += ng[g * ncl + c];
+          mg = std::max(mg, ng[g * ncl + c] * hncol[c]);
+        }
+        TRBL_REQUIRE((int64_t)gstart[g] + t < ((int64_t)1 << 31), TRBL_E_INVALID, "too many proton jump groups");
+        gstart[g + 1] = gstart[g] + t;
+      }
       m.max_hs_class = mg;
       m.dt.pg_start.upload(gstart);
-      m.dt.pg_desc.upload(gdesc);
-      m.dt.pg_cend.upload(cend);
+      jt[0].group_fill(m.dt.pj_start, jidx, m.dt.pg_start, gstart[nsd], m.dt.pg_desc, m.dt.pg_cend);
     }
-    (s == 0 ? m.dt.pj_idx : m.dt.nj_idx).upload(jidx);
-    (s == 0 ? m.dt.pj_meta : m.dt.nj_meta).upload(jmeta);
-    (s == 0 ? m.dt.pj_pack : m.dt.nj_pack).upload(pack);
-    (s == 0 ? m.pj_count : m.nj_count) = (int)jidx.size();
   }
+  TRBL_HIP(hipDeviceSynchronize());
   m.has_h = true;
 }
 
