@@ -59,9 +59,21 @@ def parse():
     p.add_argument("--trunc-spe", default="",
                    help="comma-separated single-particle energies for the truncated-start run (default: the "
                         "workload's); e.g. a wide gap above the truncation orbits")
+    p.add_argument("--large-solve", action="store_true",
+                   help="pf66 only: one TRBL solve for the 200 lowest (nb = 32, tol 1e-5 relative) with the basis "
+                        "sized to the free HBM; prints time to the 200 eigenpairs")
+    p.add_argument("--large-precision", default="mixed", choices=["mixed", "fp64"])
+    p.add_argument("--large-nb", type=int, default=32)
+    p.add_argument("--large-ls", type=int, default=320)
+    p.add_argument("--large-lm", type=int, default=0, help="0: as many as fit")
+    p.add_argument("--large-max-s", type=float, default=1000.0,
+                   help="stop after about this many seconds of iterations (max_iter from the measured rate)")
+    p.add_argument("--cpu-baseline-full", action="store_true",
+                   help="host only: the oracle's block H.V (median of 5) on the sd 2+2 and sd 6+6 workloads in full "
+                        "and on a row sample of pf44, and the oracle TRBL time to N on sd 2+2 and sd 6+6")
     p.add_argument("--sweep", action="store_true",
-                   help="block-size sweep instead of the benchmark: H.V time and TRBL solve for the 32 lowest, "
-                        "nb = 1..32, l_s = 40, l_m = max(200, 40 + 10 nb)")
+                   help="block-size sweep instead of the benchmark: H.V time against nb = 1..32 and TRBL solves "
+                        "for the 32 lowest with 160 or 320 new vectors per restart cycle and without restarts")
     return p.parse_args()
 
 
@@ -123,6 +135,63 @@ def hv_timing(model, nb, dtype, launches, torch):
     return e0.elapsed_time(e1) / 1e3 / launches
 
 
+def host_info():
+    """Host cores and CPU model (the oracle runs on these)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"nproc": avail, "cpu_count": os.cpu_count(), "cpu_model": model}
+
+
+def cpu_baseline_full():
+    """The oracle timed on the host cores: block H.V (median of 5) on sd 2+2 and sd 6+6 in full and
+    on a 20,000-row sample of pf44 (scaled to the full matrix), and the oracle TRBL (Alg. 4) time to
+    the wanted eigenpairs on sd 2+2 and sd 6+6 with the GPU bench's parameters."""
+    import numpy as np
+
+    from oracle.hamiltonian import model_from_workload, threads
+    from oracle.trbl import trbl
+    from workloads import WORKLOADS, random_block
+    res = {"host": host_info(), "oracle_threads": threads(), "hv": {}, "time_to_n": {}}
+    for name in ("sd22", "sd66", "pf44"):
+        w = WORKLOADS[name]
+        t0 = time.perf_counter()
+        m = model_from_workload(w)
+        t_build = time.perf_counter() - t0
+        V = random_block(2000, m.dim, w.nb)
+        if name == "pf44":
+            idx = np.sort(np.random.default_rng(0).choice(m.dim, 20000, replace=False))
+        else:
+            idx = np.arange(m.dim)
+        ts = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            m.apply_rows(V, idx)
+            ts.append(time.perf_counter() - t0)
+        med = float(np.median(ts))
+        res["hv"][name] = {"D": m.dim, "nb": w.nb, "rows_timed": len(idx), "median_s": med,
+                           "per_full_hv_s": med * m.dim / len(idx), "build_s": t_build}
+        print(f"# oracle H.V {name}: {med:.4f} s for {len(idx)} rows -> {med * m.dim / len(idx):.3f} s per H.V",
+              file=sys.stderr, flush=True)
+        if name in ("sd22", "sd66"):
+            t0 = time.perf_counter()
+            ev, _, info = trbl(m.apply, m.dim, random_block(1000, m.dim, w.nb), w.n_eig, w.l_s, w.l_m, w.tol)
+            t = time.perf_counter() - t0
+            res["time_to_n"][name] = {"n_eig": w.n_eig, "nb": w.nb, "l_s": w.l_s, "l_m": w.l_m, "tol": w.tol,
+                                      "s": t, "iterations": info["iterations"], "converged": bool(info["converged"])}
+            print(f"# oracle TRBL {name}: {t:.2f} s, {info['iterations']} iterations", file=sys.stderr, flush=True)
+    print(json.dumps(res), flush=True)
+
+
 def cpu_baseline(w, iterations, seconds_target=12.0):
     """The oracle's block H.V on a bounded sample of rows, scaled to one solve's H.V work."""
     import numpy as np
@@ -146,6 +215,7 @@ def cpu_baseline(w, iterations, seconds_target=12.0):
         "value": per_hv * iterations,
         "unit": "s",
         "cores": threads(),
+        **host_info(),
         "kind": "oracle",
         "sample": (f"oracle block H.V (nb={w.nb}) on {n2} random rows of {m.dim} ({t2:.1f} s), scaled to the "
                    f"full matrix ({per_hv:.1f} s per H.V) and to the {iterations} block iterations of the GPU "
@@ -154,24 +224,91 @@ def cpu_baseline(w, iterations, seconds_target=12.0):
 
 
 def sweep(model, w, torch, np):
-    """Trade-off of Sec. 4.2: block H.V time against nb (a line whose intercept is the fixed
-    generation cost) and iterations / time to the 32 lowest eigenpairs against nb."""
+    """Trade-off of Sec. 4.1 / 4.2: block H.V time against nb (a line whose intercept is the fixed
+    generation cost), and iterations / time to the 32 lowest eigenpairs against nb for three restart
+    settings: a fixed number of new vectors per restart cycle (l_m - l_s = 160 and 320) and no
+    restart at all (l_m at the device eigensolver's limit, which the solve does not reach)."""
+    nbs = (1, 2, 4, 8, 16, 32)
+    hv = {}
+    for nb in nbs:
+        hv[nb] = hv_timing(model, nb, torch.float64, 10, torch)
+        print(f"# H.V nb={nb}: {hv[nb] * 1e3:.3f} ms", file=sys.stderr, flush=True)
+    x = np.array(nbs, dtype=float)
+    slope, icpt = np.polyfit(x, np.array([hv[nb] * 1e3 for nb in nbs]), 1)
+    settings = [("cycle160", 40, lambda nb: 200), ("cycle320", 64, lambda nb: 384),
+                ("largest", 40, lambda nb: 640 + nb)]
     rows = []
-    for nb in (1, 2, 4, 8, 16, 32):
-        t_hv = hv_timing(model, nb, torch.float64, 10, torch)
-        lm = max(200, 40 + 10 * nb)  # room for ten blocks between restarts
-        ev, _, info = model.solve(nb, 32, 40, lm, 1e-8, "fp64", max_iter=20000, seed=1000, check_every=-1)
-        r = {"nb": nb, "l_m": lm, "hv_ms": t_hv * 1e3, "hv_ms_per_vector": t_hv * 1e3 / nb, "iterations": info.iterations,
-             "restarts": info.restarts, "converged": info.converged, "t_total_s": info.t_total, "t_hv_s": info.t_hv,
-             "t_orth_s": info.t_orth, "t_qr_s": info.t_qr, "t_eig_s": info.t_eig, "t_restart_s": info.t_restart,
-             "e0": float(ev[0]), "e31": float(ev[31])}
-        print("# " + json.dumps(r), file=sys.stderr, flush=True)
-        rows.append(r)
-    x = np.array([r["nb"] for r in rows], dtype=float)
-    y = np.array([r["hv_ms"] for r in rows])
-    slope, icpt = np.polyfit(x, y, 1)
+    for name, ls, lmf in settings:
+        for nb in nbs:
+            lm = lmf(nb)
+            ev, _, info = model.solve(nb, 32, ls, lm, 1e-8, "fp64", max_iter=20000, seed=1000, check_every=-1)
+            r = {"setting": name, "nb": nb, "l_s": ls, "l_m": lm, "hv_ms": hv[nb] * 1e3,
+                 "iterations": info.iterations, "matvecs": info.iterations * nb, "restarts": info.restarts,
+                 "converged": info.converged, "t_total_s": info.t_total, "t_hv_s": info.t_hv,
+                 "t_orth_s": info.t_orth, "t_qr_s": info.t_qr, "t_eig_s": info.t_eig, "t_restart_s": info.t_restart,
+                 "e0": float(ev[0]), "e31": float(ev[31])}
+            print("# " + json.dumps(r), file=sys.stderr, flush=True)
+            rows.append(r)
     print(json.dumps({"sweep": rows, "hv_fit_ms": {"intercept": icpt, "slope_per_vector": slope},
-                      "workload": w.name, "n_eig": 32, "l_s": 40, "l_m": "max(200, 40 + 10 nb)", "tol": 1e-8}))
+                      "workload": w.name, "n_eig": 32, "tol": 1e-8}))
+
+
+def large_solve(model, w, a, torch, np, t_setup, hv64, hv32):
+    """One TRBL solve of the large space for its wanted eigenpairs, the basis sized to the free
+    HBM: the stored vectors take what is left after the packed block, the FP64 work block (FP64
+    only), the final FP64 check or refinement chunks (8 GB each) and a 6 GB margin. l_m - nb is
+    capped at 640, the largest projected matrix of the device eigensolver. Progress lines of the
+    solver go to stderr; the eigenvalues and residuals are written next to the JSON line."""
+    D = model.dim
+    nb = a.large_nb
+    mixed = a.large_precision == "mixed"
+    s = 4 if mixed else 8
+    torch.cuda.empty_cache()  # the H.V timing blocks
+    free, total = torch.cuda.mem_get_info()
+    reserve = D * nb * s + (0 if mixed else D * nb * 8) + 2 * 8e9 + 6e9
+    lm_fit = int((free - reserve) // (D * s))
+    lm = a.large_lm or min(640 + nb, lm_fit) // nb * nb
+    ls = min(a.large_ls, lm - 2 * nb)
+    n_eig = min(w.n_eig, ls)
+    tol = 1e-5
+    # iteration budget from the measured H.V rate (the other per-iteration work is about half of it)
+    hv = hv32 if mixed else hv64
+    max_iter = max(8, int(a.large_max_s / (1.6 * hv * max(nb / w.nb, 0.5))))
+    print(f"# large solve: {a.large_precision}, D={D}, nb={nb}, n_eig={n_eig}, l_s={ls}, l_m={lm} "
+          f"(fits {lm_fit}), free {free / 1e9:.1f} GB of {total / 1e9:.1f} GB, max_iter {max_iter}",
+          file=sys.stderr, flush=True)
+    os.environ["TRBL_VERBOSE"] = "1"
+    t0 = time.perf_counter()
+    ev, _, info = model.solve(nb, n_eig, ls, lm, tol, a.large_precision, max_iter=max_iter, seed=1000,
+                              check_every=-1)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    os.environ["TRBL_VERBOSE"] = "0"
+    out_dir = os.path.join(ROOT, "gpurun_out")
+    os.makedirs(out_dir, exist_ok=True)
+    path = os.path.join(out_dir, f"large_{w.name}_{a.large_precision}_nb{nb}_evals.txt")
+    with open(path, "w") as f:
+        f.write(f"# {w.name} {a.large_precision} nb={nb} l_s={ls} l_m={lm} tol={tol} converged={info.converged} "
+                f"iterations={info.iterations} restarts={info.restarts} n_converged={info.n_converged}\n")
+        for x, r in zip(ev, info.resid):
+            f.write(f"{x:.17g} {r:.6g}\n")
+    out = {
+        "metric": f"s to {n_eig} converged eigenpairs ({a.large_precision})", "value": t if info.converged else None,
+        "unit": "s", "n_gpus": 1, "higher_is_better": False, "vs_baseline": None,
+        "dtype": "f32+f64" if mixed else "f64", "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.n_prot}+{w.n_neut} nucleons, orbits {list(w.orbits)}, 2M={w.twoM}, "
+                               f"D={D}, random J-coupled TBMEs sigma={w.sigma} seed {w.seed}; TRBL nb={nb}, "
+                               f"{n_eig} lowest, l_s={ls}, l_m={lm}, tol={tol} of max|theta|",
+                   "D": D, "nb": nb, "n_eig": n_eig, "l_s": ls, "l_m": lm, "tol": tol, "max_iter": max_iter},
+        "solve_s": t, "converged": info.converged, "n_converged": info.n_converged,
+        "iterations": info.iterations, "restarts": info.restarts,
+        "phases_s": {"hv": info.t_hv, "orth": info.t_orth, "qr": info.t_qr, "eig": info.t_eig,
+                     "restart": info.t_restart, "refine": info.t_refine},
+        "max_resid_rel": float(np.max(info.resid) / max(abs(ev).max(), 1e-300)),
+        "lowest": float(ev[0]), "highest_wanted": float(ev[-1]), "setup_s": t_setup,
+        "hv": {"fp64_ms": hv64 * 1e3, "fp32_ms": hv32 * 1e3}, "hbm_free_GB": free / 1e9, "evals_file": path,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def truncated_start(model, w, a, torch):
@@ -222,11 +359,12 @@ def main():
         sys.exit(2)
     from workloads import WORKLOADS
 
+    if a.cpu_baseline_full:
+        cpu_baseline_full()
+        return
     w = WORKLOADS[a.workload]
-    if w.name == "pf66" and not a.hv_only:
-        print("pf66: only --hv-only here (its FP64 basis does not fit one GPU and a mixed solve to 200 "
-              "eigenpairs takes about an hour; the pf66 tests cover restarts and FP64 against mixed)",
-              file=sys.stderr)
+    if w.name == "pf66" and not (a.hv_only or a.large_solve):
+        print("pf66: --hv-only (H.V timing) or --large-solve (one solve for the 200 lowest)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -253,6 +391,9 @@ def main():
             torch.cuda.synchronize()
         return
 
+    if a.large_solve:
+        large_solve(model, w, a, torch, np, t_setup, hv64, hv32)
+        return
     if a.sweep:
         sweep(model, w, torch, np)
         return

@@ -806,9 +806,30 @@ void update(const TA* A, int64_t lda, int m, const double* C, const TI* Bin, int
     size_t b = (size_t)(mt * 16 * ct * 16 + waves * 16 * ct * 16) * sizeof(double);
     return std::max(b, (size_t)ct * 16 * ct * 16 * sizeof(double));
   };
+  if (shm_for(4) > 160 * 1024) {
+    // C (m x nb) does not fit the LDS next to the tile: the columns of A in chunks, the first
+    // from Bin, the rest in place on Bout; the fused products after the last chunk (Gram) or
+    // separately (A^T Bout)
+    const int mmax = (int)((160 * 1024 / sizeof(double) - 4 * 16 * ct * 16) / (ct * 16)) / 16 * 16;
+    TRBL_REQUIRE(mmax >= 16 && Bin != nullptr, TRBL_E_INVALID, "update tile does not fit in LDS");
+    for (int k0 = 0; k0 < m; k0 += mmax) {
+      const int mc = std::min(mmax, m - k0);
+      const bool last = k0 + mc >= m;
+      if (k0 == 0)
+        update<TA, TI, TO>(A + k0, lda, mc, C + (size_t)k0 * nb, Bin, ldi, Bout, ldo, nb, D,
+                           last && mode == 2 ? 2 : 0, nullptr, s, st);
+      else
+        update<TA, TO, TO>(A + k0, lda, mc, C + (size_t)k0 * nb, Bout, ldo, Bout, ldo, nb, D,
+                           last && mode == 2 ? 2 : 0, nullptr, s, st);
+    }
+    if (mode == 1) {
+      TRBL_REQUIRE(Pout != nullptr, TRBL_E_INVALID, "projection output missing");
+      tn<TA, TO>(A, lda, m, Bout, ldo, nb, D, Pout, s, st);
+    }
+    return;
+  }
   const int waves = (shm_for(8) <= 160 * 1024) ? 8 : 4;
   const size_t shm = shm_for(waves);
-  TRBL_REQUIRE(shm <= 160 * 1024, TRBL_E_INVALID, "update tile does not fit in LDS");
   int G = grid_for(D, waves * 16 * 4, 1024);
   const int64_t plen = mode == 1 ? (int64_t)m * nb : (int64_t)nb * nb;
   double* part = mode ? s.partials((size_t)G * plen) : nullptr;

@@ -147,3 +147,18 @@ def test_pf44_ritz_vectors_have_integer_j():
     J = (-1 + np.sqrt(1 + 4 * j2)) / 2
     say("pf44 J values", np.round(J, 4)[:20], "max dev", np.abs(J - np.round(J)).max())
     assert np.abs(J - np.round(J)).max() <= 1e-4
+
+
+@pytest.mark.parametrize("nb", [32, 64])
+def test_sd66_wide_block_large_basis(nb):
+    """Blocks of 32 and 64 vectors with the basis at the eigensolver's limit (l_m - nb = 640):
+    the projected updates there exceed the LDS tile of one pass over the basis and run in
+    chunks of its columns. FP64 against the oracle TRBL's eigenvalues (<= 1e-8 relative)."""
+    ref = _golden("sd66")
+    w = WORKLOADS["sd66"]
+    g = _model(w)
+    ev, _, info = g.solve(nb, w.n_eig, 64, 640 + nb, w.tol, "fp64", check_every=-1)
+    rel = np.abs(ev - ref) / np.abs(ref)
+    say("sd66 nb", nb, "iterations", info.iterations, "restarts", info.restarts, "max rel err", rel.max())
+    assert info.converged
+    assert rel.max() <= 1e-8
