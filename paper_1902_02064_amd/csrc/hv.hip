@@ -101,6 +101,7 @@ static HVPlan& plan_for(const Model& m, int nb, size_t elt) {
     std::vector<int64_t> i0(1, 0);
     for (int b : kv.second) i0.push_back(i0.back() + (int64_t)m.blocks[b].dp * P->ntile * B.nchunk);
     B.nblk = (int)kv.second.size();
+    B.maxdn = maxdn;
     B.items = i0.back();
     TRBL_REQUIRE(B.items < (int64_t)1 << 31 && (B.items + 7) * B.nthr < (int64_t)1 << 32, TRBL_E_INVALID,
                  "problem too large for one launch");
@@ -185,7 +186,18 @@ static void run_hv(const Model& m, int nb, const void* V, int64_t ldv, void* W, 
   a.ntile = P.ntile;
   a.dma = a.dma && nb % P.C == 0;
   a.citem0 = P.citem0.as<int64_t>();
+  // FP64 with the pair-block tables: the rows and columns kernels write the identical-particle
+  // parts, the pair blocks add the pn part
+  bool own = false;
+  if constexpr (sizeof(T) == 8) {
+    own = m.pn.on && (double)m.dim * (double)ldv * 8.0 < 4294967296.0;  // 32-bit byte offsets into V
+    for (const auto& B : P.bins) own = own && B->mp == 1;
+  }
+  a.own = own ? 1 : 0;
   dispatch_hv<T>(a, P, s);
+  if constexpr (sizeof(T) == 8) {
+    if (own) launch_pn_tiles(m, nb, static_cast<const double*>(V), ldv, static_cast<double*>(W), ldw, s);
+  }
 }
 
 void prepare_hv_plans(const Model& m, int precision, const int* widths, int n) {

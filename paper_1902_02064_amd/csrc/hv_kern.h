@@ -41,6 +41,7 @@ struct HVArgs {
   int nnum;              // neutron number operators merged in the diagonal class (0: none)
   int C, ntile, nchunk;  // column tile width, column tiles, target chunks per row/column
   int dma;               // source rows copied by global->LDS DMA (16-byte aligned rows)
+  int own;               // identical-particle parts only (the pn part is added by the pair blocks)
   int64_t nn_total;
   const int* blk_dp;
   const int* blk_dn;
@@ -539,6 +540,64 @@ __global__ __launch_bounds__(NTB) void hv_rows_kernel(HVArgs<T> a) {
   }
 }
 
+// Own-row kernel: the neutron-neutron part and the diagonal of the rows kernel without its pn part,
+// for products whose pn part comes from the pair blocks. One workgroup per target proton row
+// (and column tile); the row is staged once in LDS (dynamic size: the widest sector of the bin).
+template <class T, int C, int NTB, bool DMA>
+__global__ __launch_bounds__(NTB) void hv_own_kernel(HVArgs<T> a) {
+  using L = Tile<T, C>;
+  extern __shared__ __align__(256) char B0[];
+  const int64_t nitems = a.bin_item0[a.bin_nblk];
+  const int64_t item = xcd_item(blockIdx.x, nitems);
+  if (item >= nitems) return;
+  const int bi = find_block(a.bin_item0, a.bin_nblk, item);
+  const int b = a.bin_blocks[bi];
+  int64_t rel = item - a.bin_item0[bi];
+  const int tc = (int)(rel % a.nchunk);
+  rel /= a.nchunk;
+  const int ct = (int)(rel % a.ntile);
+  const int pl = (int)(rel / a.ntile);
+  const int nthr = blockDim.x, tid = threadIdx.x;
+  const int c0 = ct * C, cvalid = min(C, a.nb - c0);
+  const int dn = a.blk_dn[b];
+  const int64_t off = a.blk_off[b];
+  const int gn0 = a.blk_n0[b];
+  const int tlo = tc * nthr;
+  if (tlo >= dn) return;
+  const T* src = a.V + (off + (int64_t)pl * dn) * a.ldv + c0;
+  if constexpr (DMA) stage_dma<T, C>(B0, src, a.ldv, dn);
+  else stage_sync<T, C>(B0, src, a.ldv, dn, cvalid);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  const int ln = tlo + tid;
+  if (ln >= dn) return;
+  T acc[C];
+#pragma unroll
+  for (int c = 0; c < C; c++) acc[c] = T(0);
+  const int sl = a.blk_nslice0[b] + ln / 64, lo = ln % 64;
+  const int base = a.ne_off[sl], wd = a.ne_w[sl];
+  for (int k = 0; k < wd; k += 4) {
+    int cc[4];
+    T vv[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int at = base + (k + u) * 64 + lo;
+      cc[u] = k + u < wd ? a.ne_col[at] : 0;
+      vv[u] = k + u < wd ? a.ne_val[at] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) gather_row<T, C>(acc, vv[u], B0, cc[u] * L::RB);
+  }
+  T* w = a.W + (off + (int64_t)pl * dn + a.nlane[gn0 + ln]) * a.ldw + c0;
+#pragma unroll
+  for (int t = 0; t < L::CPR; t++) {
+    const int k = t ^ L::rot();
+#pragma unroll
+    for (int v = 0; v < L::VPC; v++)
+      if (k * L::VPC + v < cvalid) w[k * L::VPC + v] = acc[t * L::VPC + v];
+  }
+}
+
 // Columns kernel: proton-proton part, W[:, n] += Hpp V[:, n] for one neutron column n of one
 // block; the column (all proton rows of the block, one column tile) is staged in LDS and one
 // lane owns one target proton row p'.
@@ -616,6 +675,14 @@ static void dispatch_cols(HVArgs<T>& a, const HVPlan& P, hipStream_t s) {
   else launch_cols<T, CC, 4>(a, P, s);
 }
 
+template <class T, int C, int NTB>
+static void launch_own(const HVArgs<T>& a, const HVBin& B, hipStream_t s) {
+  const dim3 grid((unsigned)((B.items + 7) / 8 * 8)), block(B.nthr);
+  const size_t shm = (size_t)B.maxdn * C * sizeof(T);
+  if (a.dma) hipLaunchKernelGGL((hv_own_kernel<T, C, NTB, true>), grid, block, shm, s, a);
+  else hipLaunchKernelGGL((hv_own_kernel<T, C, NTB, false>), grid, block, shm, s, a);
+}
+
 template <class T, int C>
 static void dispatch_c(HVArgs<T>& a, const HVPlan& P, hipStream_t s) {
   for (const auto& Bp : P.bins) {
@@ -624,6 +691,15 @@ static void dispatch_c(HVArgs<T>& a, const HVPlan& P, hipStream_t s) {
     a.bin_blocks = B.blocks.as<int>();
     a.bin_item0 = B.item0.as<int64_t>();
     a.bin_nblk = B.nblk;
+    if constexpr (sizeof(T) == 8) {
+      if (a.own) {
+        TRBL_REQUIRE(B.mp == 1, TRBL_E_INVALID, "own-row plan with several targets per lane");
+        if (B.ntb == 256) launch_own<T, C, 256>(a, B, s);
+        else if (B.ntb == 768) launch_own<T, C, 768>(a, B, s);
+        else launch_own<T, C, 1024>(a, B, s);
+        continue;
+      }
+    }
 #define TRBL_ROWS_RB(NTB)                                                   \
   (B.rb_kb == 24   ? launch_rows<T, C, NTB, 24>(a, B, s)                    \
    : B.rb_kb == 36 ? launch_rows<T, C, NTB, 36>(a, B, s)                    \

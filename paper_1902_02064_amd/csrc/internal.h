@@ -136,6 +136,7 @@ struct HVBin {
   int nthr = 64, ntb = 256, nchunk = 1, rb_kb = 24, nblk = 0;  // width, its launch bound, chunks, LDS row KB
   int mp = 1;                                                    // targets per lane (1024-wide, 72 KB bins)
   int nr = 16;                                                   // neutron jumps per class held in registers
+  int maxdn = 0;                                                 // widest target sector of the bin
   int64_t items = 0;
   DevBuf blocks, item0;  // block ids of the bin, first work item of each (nblk + 1)
 };
@@ -146,6 +147,29 @@ struct HVPlan {
   size_t shm_c = 0;
   DevBuf citem0;
   std::vector<std::unique_ptr<HVBin>> bins;
+};
+
+// Proton-neutron part of H.V as dense pair blocks (pntile.hip). A proton determinant with one
+// particle removed is a proton core K_p (the same for neutrons); every pn term moves one proton
+// and one neutron, so it links the states K_p+x, K_n+u and K_p+y, K_n+v of exactly one core pair.
+// With the pair states (x,u) of one total 2m listed once, the pn part is a sum over core pairs
+// of the symmetric block H_M[(x,u)][(y,v)] restricted to the pairs outside the cores.
+struct PNTiles {
+  bool on = false;
+  int S = 0;                 // contribution slots per basis state: n_prot * n_neut
+  int nk = 0;                // pair blocks (2M of a pair from -2 tjmax to 2 tjmax)
+  int nrect = 0;             // core-group rectangles (fixed core 2M and parity on both sides)
+  int ncore[2] = {0, 0};
+  int max_pairs = 0;         // widest pair block
+  int tpb = 256;             // most core pairs of one work item
+  int64_t items = 0;         // workgroups of one launch
+  DevBuf cw[2], rk[2];       // core words; [core * ns + state]: position of state << 24 | local index of core + state, -1 inside
+  DevBuf pr_off, pr_xu;      // pair blocks: x | u << 8
+  DevBuf hb_off, hb;         // per pair block: D2 x D2 FP64 matrix, row = target pair
+  DevBuf rect, rblk, item0;  // rectangles (pair block, rblk start), per rectangle and pair the target block
+                             // (-1: none), work items (rectangle, proton core, first neutron core, count)
+  DevBuf boff;               // block offsets as 32-bit integers
+  DevBuf z;                  // slot buffer [S][D][16] of one 16-column tile
 };
 
 struct MTerm {  // m-scheme two-body term c+_a c+_b c_d c_c (species-local state indices)
@@ -191,6 +215,7 @@ struct Model {
   int fly_s = 1;     // the occupied species
   int fly_half = 0;  // m-states in the low part of the two-level ranking
   mutable DevBuf fly_buf[2];  // V and W in the internal order (FP32, FP64)
+  mutable PNTiles pn;         // FP64 pn part as dense pair blocks (when its slot buffer fits)
 };
 
 // host helpers (model.cpp)
@@ -203,6 +228,11 @@ void build_fly_terms(Model& m);
 void launch_fly(const Model& m, int precision, int nb, const void* V, int64_t ldv, void* W, int64_t ldw,
                 hipStream_t s, const double* mask = nullptr);
 double clebsch(int tj1, int tm1, int tj2, int tm2, int tJ, int tM);
+
+// pn part by pair blocks (pntile.hip): tables built with the Hamiltonian; the product adds
+// the pn part of H V to W (FP64, W already holding the identical-particle parts)
+void build_pn_tiles(Model& m);
+void launch_pn_tiles(const Model& m, int nb, const double* V, int64_t ldv, double* W, int64_t ldw, hipStream_t s);
 
 // device launchers (hv.hip)
 void launch_apply(const Model& m, int precision, int nb, const void* V, int64_t ldv, void* W, int64_t ldw,

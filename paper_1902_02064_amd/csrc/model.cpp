@@ -671,6 +671,7 @@ void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const
     }
   }
   TRBL_HIP(hipDeviceSynchronize());
+  build_pn_tiles(m);
   m.has_h = true;
 }
 

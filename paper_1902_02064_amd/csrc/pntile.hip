@@ -1,0 +1,421 @@
+// Proton-neutron part of the block H.V (App. B) as dense pair blocks on the matrix cores.
+//
+// Every pn term c+_a(p) c+_b(n) c_d(n) c_c(p) moves one proton (c -> a) and one neutron (d -> b).
+// Acting on a basis state it keeps the other protons, a core K_p of n_prot - 1 particles, and the
+// other neutrons, a core K_n. Take the pair states (x, u), x a proton m-state and u a neutron
+// m-state, grouped by their total 2m. For a fixed core pair (K_p, K_n) the states K_p+x, K_n+u
+// with x outside K_p and u outside K_n, and 2m(x) + 2m(u) = 2M - 2M(K_p) - 2M(K_n), are linked
+// by the pn terms as a dense symmetric block: the m-scheme pn matrix H_M[(x,u)][(y,v)] of that
+// pair 2m, restricted to the allowed pairs. The Jordan-Wigner sign of c+_x c_y on K_p+y is
+// sigma(K_p, x) sigma(K_p, y), sigma(K, s) = (-1)^(occupied states of K below s), and the same on
+// the neutron side, so the sign of an element factorises into a target and a source sign.
+//
+// Each term is counted in exactly one core pair (the core is the set of spectator nucleons;
+// a = c is a proton number operator, and its core is the target minus a), so the pn part of W is
+//   W[t] += sum over the n_prot * n_neut core pairs of t of  s_t (H_M (s V))[t].
+// A wavefront takes one core pair: it lists the allowed pairs with a ballot, gathers the source
+// rows (16 columns, one 128-byte line each) with their signs, multiplies by the block of H_M on
+// the matrix cores (v_mfma_f64_16x16x4f64), and writes each target row into the slot named by
+// the positions of x in the target's proton word and of u in its neutron word. Every slot of
+// every basis state is written exactly once per product, so the second kernel sums the slots
+// into W in a fixed order: no atomics, and the result does not depend on scheduling.
+#include <algorithm>
+#include <cstdlib>
+#include <map>
+
+#include "internal.h"
+
+namespace trbl {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int PN_TPB = 256;       // most core pairs of one work item
+constexpr int PN_MAXPAIR = 64;    // widest pair block (one ballot)
+
+struct PNTileArgs {
+  const double* V;
+  double* Z;
+  int c0, cval;  // column tile: first column, valid columns (<= 16)
+  int ns, nneut, D, vrow;  // vrow: bytes per row of V
+  const int* rkp;  // [core * ns + state]: position << 24 | local index of core + state, -1 inside
+  const int* rkn;
+  const int* blk_off;  // block offsets (the tables are used only while D < 2^31)
+  const int* blk_dn;
+  const int* pr_off;
+  const int* pr_xu;
+  const int* hb_off;
+  const double* hb;
+  const int* rect;    // per rectangle: pair block, first entry of its list in rblk
+  const int* rblk;    // per rectangle and pair: block of the target's sectors, -1 if none
+  const int4* items;  // per work item: rectangle, proton core, first neutron core, count
+  int nitems;
+};
+
+// work item -> position: consecutive items (one proton core) go to one XCD
+__device__ __forceinline__ int pn_xcd_item(int bid, int n) {
+  const int per = (n + 7) / 8;
+  return (bid % 8) * per + bid / 8;
+}
+
+__device__ __forceinline__ double flip_if(double x, unsigned s) {
+  return __hiloint2double(__double2hiint(x) ^ (int)(s << 31), __double2loint(x));
+}
+
+// The product of one core pair: Z rows of its d allowed targets = (staged block) x (signed source
+// rows), DTM row tiles of 16 targets at most (d <= 16 DTM); sources k = 4 ks + l / 16 in groups
+// of 8 steps whose loads are issued together.
+template <int DTM>
+__device__ __forceinline__ void tile_product(const PNTileArgs& a, const double* Hs, const unsigned* Rv,
+                                             const unsigned* Rz, const int* Pi, int d, int HW, int c, int kq,
+                                             bool cok, unsigned cb, const char* Vb, char* Zb) {
+  const int KS = (d + 3) >> 2, DT = (d + 15) >> 4;
+  int tb[DTM];
+  d4 acc[DTM];
+#pragma unroll
+  for (int mt = 0; mt < DTM; mt++) {
+    tb[mt] = Pi[16 * mt + c] * HW;
+    acc[mt] = d4{0.0, 0.0, 0.0, 0.0};
+  }
+#pragma unroll
+  for (int h = 0; h < DTM / 2; h++) {
+    double bop[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      const unsigned o = Rv[4 * (8 * h + j) + kq];
+      bop[j] = flip_if(*reinterpret_cast<const double*>(Vb + ((o & ~1u) + cb)), o & 1u);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      if (8 * h + j < KS) {
+        const int pk = Pi[4 * (8 * h + j) + kq];
+        double av[DTM];
+#pragma unroll
+        for (int mt = 0; mt < DTM; mt++) av[mt] = Hs[tb[mt] + pk];
+#pragma unroll
+        for (int mt = 0; mt < DTM; mt++)
+          if (mt < DT) acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mt], bop[j], acc[mt], 0, 0, 0);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // D: lane l, register v holds target 16 mt + l / 16 + 4 v, column c
+#pragma unroll
+  for (int mt = 0; mt < DTM; mt++) {
+    if (mt < DT) {
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int i = 16 * mt + kq + 4 * v;
+        const unsigned z = Rz[i];
+        if (i < d && cok) *reinterpret_cast<double*>(Zb + ((z & ~127u) + (unsigned)c * 8u)) = flip_if(acc[mt][v], z & 1u);
+      }
+    }
+  }
+}
+
+// One work item: a proton core K_p and up to PN_TPB neutron cores of one (2M, parity) group; the
+// four wavefronts take every fourth core pair. Per core pair the allowed pairs are listed in LDS
+// (V byte offset | source sign, slot byte offset | target sign, pair index); the list is padded
+// to 64 entries with a valid row and the pair index D2, whose row and column of the staged block
+// are zero, so the products need no masks.
+__global__ __launch_bounds__(256, 4) void pn_tile_kernel(PNTileArgs a) {
+  __shared__ double Hs[(PN_MAXPAIR + 1) * (PN_MAXPAIR + 1)];
+  __shared__ int Po[PN_MAXPAIR];  // per pair: offset of its block (-1: no block)
+  __shared__ int Pd[PN_MAXPAIR];  // per pair: neutron sector size of its block
+  __shared__ int Ps[PN_MAXPAIR];  // per pair: x | u << 8
+  __shared__ unsigned Rv[4][64];
+  __shared__ unsigned Rz[4][64];
+  __shared__ int Pi[4][64];
+  const int item = pn_xcd_item(blockIdx.x, a.nitems);
+  if (item >= a.nitems) return;
+  const int4 it = a.items[item];
+  const int k = a.rect[2 * it.x], rb0 = a.rect[2 * it.x + 1];
+  const int q0 = a.pr_off[k], D2 = a.pr_off[k + 1] - q0, HW = D2 + 1;
+  const double* hg = a.hb + a.hb_off[k];
+  for (int e = threadIdx.x; e < HW * HW; e += 256) {
+    const int i = e / HW, j = e - i * HW;
+    Hs[e] = (i < D2 && j < D2) ? hg[i * D2 + j] : 0.0;
+  }
+  for (int e = threadIdx.x; e < D2; e += 256) {
+    Ps[e] = a.pr_xu[q0 + e];
+    const int b = a.rblk[rb0 + e];
+    Po[e] = b >= 0 ? a.blk_off[b] : -1;
+    Pd[e] = b >= 0 ? a.blk_dn[b] : 0;
+  }
+  __syncthreads();
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int c = l & 15, kq = l >> 4;
+  const bool cok = c < a.cval;
+  const unsigned cb = (unsigned)(a.c0 + min(c, a.cval - 1)) * 8u;  // column byte; beyond the tile: a valid column
+  const int lp = min(l, D2 - 1);
+  const int xu = Ps[lp], us = xu >> 8;
+  const int poff = Po[lp], pdn = Pd[lp];
+  const int rp = a.rkp[it.y * a.ns + (xu & 255)];  // the proton core is fixed for the item
+  const bool lok = l < D2 && poff >= 0 && rp >= 0;
+  const char* Vb = reinterpret_cast<const char*>(a.V);
+  char* Zb = reinterpret_cast<char*>(a.Z);
+  int cn = it.z + w;
+  const int cend = it.z + it.w;
+  int rnn = cn < cend ? a.rkn[cn * a.ns + us] : -1;  // loaded one core pair ahead
+  for (; cn < cend; cn += 4) {
+    const int rn = rnn;
+    if (cn + 4 < cend) rnn = a.rkn[(cn + 4) * a.ns + us];
+    // lane l: pair l of the block, allowed when both states lie outside the cores and the
+    // target's sectors form a block of the space
+    const bool ok = lok && rn >= 0;
+    const uint64_t mask = __ballot(ok);
+    const int d = __popcll(mask);
+    if (d == 0) continue;  // uniform
+    const int below = __popcll(mask & ((1ull << l) - 1));
+    const int bp = rp >> 24, bn = rn >> 24;
+    const int row = poff + (rp & 0xFFFFFF) * pdn + (rn & 0xFFFFFF);
+    const unsigned sg = (unsigned)((bp + bn) & 1);
+    const int lead = __builtin_amdgcn_readlane(row, __builtin_ctzll(mask));
+    if (ok) {
+      Rv[w][below] = (unsigned)row * (unsigned)a.vrow | sg;
+      Rz[w][below] = ((unsigned)((bp * a.nneut + bn) * a.D + row) << 7) | sg;
+      Pi[w][below] = l;
+    } else {  // padding: a valid row, the zero pair
+      const int pad = d + l - below;
+      Rv[w][pad] = (unsigned)lead * (unsigned)a.vrow;
+      Pi[w][pad] = D2;
+    }
+    // the lists are written and read by this wavefront only: LDS operations of one wavefront
+    // complete in order, so only the compiler must keep them in place
+    __builtin_amdgcn_wave_barrier();
+    if (d <= 32) tile_product<2>(a, Hs, Rv[w], Rz[w], Pi[w], d, HW, c, kq, cok, cb, Vb, Zb);
+    else tile_product<4>(a, Hs, Rv[w], Rz[w], Pi[w], d, HW, c, kq, cok, cb, Vb, Zb);
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// W[t][c0 + c] += sum of the S slots of t, in slot order
+__global__ void pn_reduce_kernel(const double* __restrict__ Z, int S, int64_t D, double* __restrict__ W, int64_t ldw,
+                                 int c0, int cval) {
+  const int64_t n = D * 16;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e & 15);
+    if (c >= cval) continue;
+    const int64_t t = e >> 4;
+    double s = 0.0;
+    for (int k = 0; k < S; k++) s += Z[((int64_t)k * D + t) * 16 + c];
+    W[t * ldw + c0 + c] += s;
+  }
+}
+
+int64_t binom(int n, int k) {
+  if (k < 0 || k > n) return 0;
+  long double r = 1.0L;
+  for (int i = 0; i < k; i++) r = r * (n - i) / (i + 1);
+  return (int64_t)(r + 0.5L);
+}
+
+}  // namespace
+
+void build_pn_tiles(Model& m) {
+  PNTiles& T = m.pn;
+  T.on = false;
+  T.z.release();
+  const char* env = std::getenv("TRBL_PN_TILES");
+  if (env && env[0] == '0') return;
+  if (m.fly || m.n_prot == 0 || m.n_neut == 0) return;
+  const int ns = m.ns, tj = m.cl.tjmax;
+  const int nk = 2 * tj + 1;
+  // pair blocks by pair 2m: (x, u) with 2m(x) + 2m(u) = 2 (k - tj)
+  std::vector<std::vector<int>> pairs(nk);
+  std::vector<int> pid(ns * ns, -1);
+  for (int x = 0; x < ns; x++)
+    for (int u = 0; u < ns; u++) {
+      const int k = (m.st_tm[x] + m.st_tm[u] + 2 * tj) / 2;
+      pid[x * ns + u] = (int)pairs[k].size();
+      pairs[k].push_back(x | (u << 8));
+    }
+  int maxp = 0;
+  for (auto& v : pairs) maxp = std::max(maxp, (int)v.size());
+  if (maxp > PN_MAXPAIR) return;
+  std::vector<int> pr_off(nk + 1, 0), pr_xu, hb_off(nk + 1, 0);
+  for (int k = 0; k < nk; k++) {
+    pr_off[k + 1] = pr_off[k] + (int)pairs[k].size();
+    hb_off[k + 1] = hb_off[k] + (int)(pairs[k].size() * pairs[k].size());
+    pr_xu.insert(pr_xu.end(), pairs[k].begin(), pairs[k].end());
+  }
+  std::vector<double> hb(hb_off[nk], 0.0);
+  for (const MTerm& t : m.terms_pn) {  // c+_a(p) c+_b(n) c_d(n) c_c(p): target pair (a, b), source pair (c, d)
+    const int k = (m.st_tm[t.a] + m.st_tm[t.b] + 2 * tj) / 2;
+    const int kc = (m.st_tm[t.c] + m.st_tm[t.d] + 2 * tj) / 2;
+    TRBL_REQUIRE(k == kc, TRBL_E_INVALID, "pn term breaks M conservation");
+    const int D2 = (int)pairs[k].size();
+    hb[hb_off[k] + pid[t.a * ns + t.b] * D2 + pid[t.c * ns + t.d]] += t.h;
+  }
+  // cores of each species: all (N - 1)-subsets, grouped by (2M, parity)
+  struct Group {
+    int tm, par, start, count;
+  };
+  std::vector<Group> groups[2];
+  std::vector<uint64_t> cw[2];
+  std::vector<int> rk[2];
+  std::map<std::pair<int, int>, int> secid[2];
+  for (int s = 0; s < 2; s++) {
+    const Species& S = m.sp[s];
+    for (int q = 0; q < (int)S.sectors.size(); q++) secid[s][{S.sectors[q].twoM, S.sectors[q].par}] = q;
+    const int nc = S.npart - 1;
+    if (binom(ns, nc) > (1 << 21)) return;
+    std::map<std::pair<int, int>, std::vector<uint64_t>> by;
+    auto visit = [&](uint64_t w) {
+      int tm = 0, ls = 0;
+      for (uint64_t x = w; x; x &= x - 1) {
+        const int st = __builtin_ctzll(x);
+        tm += m.st_tm[st];
+        ls += m.orbits[m.st_orb[st]].l;
+      }
+      by[{tm, (ls & 1) ? -1 : 1}].push_back(w);
+    };
+    if (nc == 0) {
+      visit(0);
+    } else {
+      uint64_t w = (1ull << nc) - 1;
+      const uint64_t limit = ns == 64 ? 0ull : (1ull << ns);
+      while (true) {
+        visit(w);
+        const uint64_t lo = w & (~w + 1), hi = w + lo;
+        if (hi == 0) break;
+        const uint64_t nw = (((hi ^ w) >> 2) / lo) | hi;
+        if ((ns < 64 && nw >= limit) || nw <= w) break;
+        w = nw;
+      }
+    }
+    for (auto& kv : by) {
+      groups[s].push_back({kv.first.first, kv.first.second, (int)cw[s].size(), (int)kv.second.size()});
+      for (uint64_t w : kv.second) {
+        cw[s].push_back(w);
+        for (int st = 0; st < ns; st++) {
+          if ((w >> st) & 1) {
+            rk[s].push_back(-1);
+            continue;
+          }
+          const auto it = S.index.find(w | (1ull << st));
+          if (it == S.index.end()) {  // sector not stored: no block of the space holds it
+            rk[s].push_back(-1);
+            continue;
+          }
+          const int q = S.sector_of[it->second];
+          const int loc = it->second - S.sectors[q].start;
+          TRBL_REQUIRE(loc < (1 << 24), TRBL_E_INVALID, "sector too large for the pair-block tables");
+          rk[s].push_back((__builtin_popcountll(w & ((1ull << st) - 1)) << 24) | loc);
+        }
+      }
+    }
+  }
+  // block of (proton sector, neutron sector)
+  const int nnsec = (int)m.sp[1].sectors.size();
+  std::vector<int> bos(m.sp[0].sectors.size() * nnsec, -1);
+  for (size_t b = 0; b < m.blocks.size(); b++) bos[m.blocks[b].psec * nnsec + m.blocks[b].nsec] = (int)b;
+  auto stpar = [&](int st) { return (m.orbits[m.st_orb[st]].l & 1) ? -1 : 1; };
+  // rectangles of core groups whose pair block reaches some block of the space
+  std::vector<int> rect, rblk;
+  std::vector<int> rect_of;  // per (proton group, neutron group): rectangle or -1
+  for (const Group& gp : groups[0])
+    for (const Group& gn : groups[1]) {
+      rect_of.push_back(-1);
+      const int tmp = m.twoM - gp.tm - gn.tm;
+      if (tmp < -2 * tj || tmp > 2 * tj) continue;
+      const int k = (tmp + 2 * tj) / 2;
+      bool any = false;
+      std::vector<int> pb;
+      for (int xu : pairs[k]) {
+        const int x = xu & 255, u = xu >> 8;
+        auto ip = secid[0].find({gp.tm + m.st_tm[x], gp.par * stpar(x)});
+        auto in = secid[1].find({gn.tm + m.st_tm[u], gn.par * stpar(u)});
+        const int b = (ip != secid[0].end() && in != secid[1].end()) ? bos[ip->second * nnsec + in->second] : -1;
+        pb.push_back(b);
+        any = any || b >= 0;
+      }
+      if (!any) continue;
+      rect_of.back() = (int)(rect.size() / 2);
+      rect.insert(rect.end(), {k, (int)rblk.size()});
+      rblk.insert(rblk.end(), pb.begin(), pb.end());
+    }
+  if (rect.empty()) return;
+  // work items: per proton core, per neutron group with a rectangle, up to PN_TPB neutron cores
+  std::vector<int> items;
+  const int ngn = (int)groups[1].size();
+  for (int ip = 0; ip < (int)groups[0].size(); ip++)
+    for (int cp = groups[0][ip].start; cp < groups[0][ip].start + groups[0][ip].count; cp++)
+      for (int in = 0; in < ngn; in++) {
+        const int r = rect_of[ip * ngn + in];
+        if (r < 0) continue;
+        const Group& gn = groups[1][in];
+        for (int c0 = 0; c0 < gn.count; c0 += PN_TPB)
+          items.insert(items.end(), {r, cp, gn.start + c0, std::min(PN_TPB, gn.count - c0)});
+      }
+  TRBL_REQUIRE(items.size() / 4 < ((size_t)1 << 31) / 256, TRBL_E_INVALID, "too many core pairs for one launch");
+  // the slot buffer: S slots of 16 FP64 columns per basis state, sized within a quarter of the
+  // free device memory (larger spaces keep the jump-list kernel)
+  const int S = m.n_prot * m.n_neut;
+  const size_t zbytes = (size_t)S * (size_t)m.dim * 16 * sizeof(double);
+  // 32-bit byte offsets in the kernel: the slot buffer and V (rows of at most 64 columns) must
+  // stay below 4 GiB
+  if ((double)zbytes >= 4294967296.0 || (double)m.dim * 64 * 8 >= 4294967296.0) return;
+  size_t fr = 0, tot = 0;
+  TRBL_HIP(hipMemGetInfo(&fr, &tot));
+  if (zbytes > fr / 4) return;
+  T.S = S;
+  T.nk = nk;
+  T.nrect = (int)(rect.size() / 2);
+  T.ncore[0] = (int)cw[0].size();
+  T.ncore[1] = (int)cw[1].size();
+  T.max_pairs = maxp;
+  T.tpb = PN_TPB;
+  T.items = (int64_t)(items.size() / 4);
+  T.cw[0].upload(cw[0]);
+  T.cw[1].upload(cw[1]);
+  T.rk[0].upload(rk[0]);
+  T.rk[1].upload(rk[1]);
+  T.pr_off.upload(pr_off);
+  T.pr_xu.upload(pr_xu);
+  T.hb_off.upload(hb_off);
+  T.hb.upload(hb);
+  T.rect.upload(rect);
+  T.rblk.upload(rblk);
+  T.item0.upload(items);
+  std::vector<int> boff32(m.blocks.size());
+  for (size_t b = 0; b < m.blocks.size(); b++) boff32[b] = (int)m.blocks[b].off;
+  T.boff.upload(boff32);
+  T.z.alloc(zbytes);
+  T.on = true;
+}
+
+void launch_pn_tiles(const Model& m, int nb, const double* V, int64_t ldv, double* W, int64_t ldw, hipStream_t s) {
+  const PNTiles& T = m.pn;
+  PNTileArgs a{};
+  a.V = V;
+  a.Z = T.z.as<double>();
+  a.ns = m.ns;
+  a.nneut = m.n_neut;
+  a.D = (int)m.dim;
+  a.vrow = (int)(ldv * 8);
+  a.rkp = T.rk[0].as<int>();
+  a.rkn = T.rk[1].as<int>();
+  a.blk_off = T.boff.as<int>();
+  a.blk_dn = m.dt.blk_dn.as<int>();
+  a.pr_off = T.pr_off.as<int>();
+  a.pr_xu = T.pr_xu.as<int>();
+  a.hb_off = T.hb_off.as<int>();
+  a.hb = T.hb.as<double>();
+  a.rect = T.rect.as<int>();
+  a.rblk = T.rblk.as<int>();
+  a.items = T.item0.as<int4>();
+  a.nitems = (int)T.items;
+  const unsigned grid = (unsigned)((T.items + 7) / 8 * 8);
+  for (int c0 = 0; c0 < nb; c0 += 16) {
+    a.c0 = c0;
+    a.cval = std::min(16, nb - c0);
+    hipLaunchKernelGGL(pn_tile_kernel, dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(pn_reduce_kernel, dim3(elementwise_grid(m.dim * 16)), dim3(256), 0, s, (const double*)a.Z, T.S,
+                       m.dim, W, ldw, c0, a.cval);
+  }
+  TRBL_HIP(hipGetLastError());
+}
+
+}  // namespace trbl
