@@ -194,9 +194,21 @@ static void run_hv(const Model& m, int nb, const void* V, int64_t ldv, void* W, 
     for (const auto& B : P.bins) own = own && B->mp == 1;
   }
   a.own = own ? 1 : 0;
+  // the pn part goes to the slot buffer; when one 16-column tile covers the product it is written
+  // first and the own-row kernel sums it into W, else it is added by its own pass after the
+  // identical-particle parts
+  const bool fused = own && P.C == 16 && nb <= 16;
+  if constexpr (sizeof(T) == 8) {
+    if (fused) {
+      launch_pn_tiles(m, nb, static_cast<const double*>(V), ldv, static_cast<double*>(W), ldw, s, false);
+      a.zs = m.pn.S;
+      a.zstride = m.dim * 16;
+      a.zbuf = m.pn.z.as<double>();
+    }
+  }
   dispatch_hv<T>(a, P, s);
   if constexpr (sizeof(T) == 8) {
-    if (own) launch_pn_tiles(m, nb, static_cast<const double*>(V), ldv, static_cast<double*>(W), ldw, s);
+    if (own && !fused) launch_pn_tiles(m, nb, static_cast<const double*>(V), ldv, static_cast<double*>(W), ldw, s, true);
   }
 }
 

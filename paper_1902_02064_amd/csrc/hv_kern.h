@@ -42,6 +42,9 @@ struct HVArgs {
   int C, ntile, nchunk;  // column tile width, column tiles, target chunks per row/column
   int dma;               // source rows copied by global->LDS DMA (16-byte aligned rows)
   int own;               // identical-particle parts only (the pn part is added by the pair blocks)
+  int zs;                // own-row kernel: slots of the pair-block buffer summed into W (0: none)
+  int64_t zstride;       // elements between slots of that buffer ([slot][D][16] FP64)
+  const double* zbuf;
   int64_t nn_total;
   const int* blk_dp;
   const int* blk_dn;
@@ -570,12 +573,12 @@ __global__ __launch_bounds__(NTB) void hv_own_kernel(HVArgs<T> a) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   const int ln = tlo + tid;
-  if (ln >= dn) return;
+  const bool live = ln < dn;
   T acc[C];
 #pragma unroll
   for (int c = 0; c < C; c++) acc[c] = T(0);
-  const int sl = a.blk_nslice0[b] + ln / 64, lo = ln % 64;
-  const int base = a.ne_off[sl], wd = a.ne_w[sl];
+  const int sl = a.blk_nslice0[b] + min(ln, dn - 1) / 64, lo = ln % 64;
+  const int base = a.ne_off[sl], wd = live ? a.ne_w[sl] : 0;
   for (int k = 0; k < wd; k += 4) {
     int cc[4];
     T vv[4];
@@ -588,6 +591,50 @@ __global__ __launch_bounds__(NTB) void hv_own_kernel(HVArgs<T> a) {
 #pragma unroll
     for (int u = 0; u < 4; u++) gather_row<T, C>(acc, vv[u], B0, cc[u] * L::RB);
   }
+  if constexpr (sizeof(T) == 8 && C == 16) {
+    if (a.zs > 0) {
+      // the pn part from the pair-block slots: park the rows in LDS (target order), then stream the
+      // slots of the proton row's dn targets in address order and write W once
+      __syncthreads();  // every lane has read its staged source rows
+      if (live) {
+        const int tg = a.nlane[gn0 + ln];
+#pragma unroll
+        for (int t = 0; t < L::CPR; t++)
+          *reinterpret_cast<RowChunk<T>*>(B0 + L::at(tg, t ^ L::rot())) = RowChunk<T>{acc[2 * t], acc[2 * t + 1]};
+      }
+      __syncthreads();
+      const int64_t r0 = off + (int64_t)pl * dn;
+      const int lo_t = tlo, hi_t = min(dn, tlo + nthr);
+      for (int e = lo_t * L::CPR + tid; e < hi_t * L::CPR; e += nthr) {
+        const int t = e / L::CPR, k = e % L::CPR;
+        double2 v = *reinterpret_cast<const double2*>(B0 + L::at(t, k));
+        const double* z = a.zbuf + (r0 + t) * 16 + 2 * k;
+        typedef double dv2 __attribute__((ext_vector_type(2)));
+        int q = 0;
+        for (; q + 8 <= a.zs; q += 8) {  // eight slots in flight, summed in slot order
+          dv2 zq[8];
+#pragma unroll
+          for (int j = 0; j < 8; j++)
+            zq[j] = __builtin_nontemporal_load(reinterpret_cast<const dv2*>(z + (q + j) * a.zstride));
+#pragma unroll
+          for (int j = 0; j < 8; j++) {
+            v.x += zq[j].x;
+            v.y += zq[j].y;
+          }
+        }
+        for (; q < a.zs; q++) {
+          const dv2 zq = __builtin_nontemporal_load(reinterpret_cast<const dv2*>(z + q * a.zstride));
+          v.x += zq.x;
+          v.y += zq.y;
+        }
+        T* w = a.W + (r0 + t) * a.ldw + c0 + 2 * k;
+        if (2 * k < cvalid) w[0] = v.x;
+        if (2 * k + 1 < cvalid) w[1] = v.y;
+      }
+      return;
+    }
+  }
+  if (!live) return;
   T* w = a.W + (off + (int64_t)pl * dn + a.nlane[gn0 + ln]) * a.ldw + c0;
 #pragma unroll
   for (int t = 0; t < L::CPR; t++) {

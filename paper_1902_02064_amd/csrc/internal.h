@@ -232,7 +232,9 @@ double clebsch(int tj1, int tm1, int tj2, int tm2, int tJ, int tM);
 // pn part by pair blocks (pntile.hip): tables built with the Hamiltonian; the product adds
 // the pn part of H V to W (FP64, W already holding the identical-particle parts)
 void build_pn_tiles(Model& m);
-void launch_pn_tiles(const Model& m, int nb, const double* V, int64_t ldv, double* W, int64_t ldw, hipStream_t s);
+// (reduce false: the last 16-column tile stays in the slot buffer for the own-row kernel to sum)
+void launch_pn_tiles(const Model& m, int nb, const double* V, int64_t ldv, double* W, int64_t ldw, hipStream_t s,
+                     bool reduce);
 
 // device launchers (hv.hip)
 void launch_apply(const Model& m, int precision, int nb, const void* V, int64_t ldv, void* W, int64_t ldw,

@@ -66,40 +66,46 @@ __device__ __forceinline__ double flip_if(double x, unsigned s) {
 // The product of one core pair: Z rows of its d allowed targets = (staged block) x (signed source
 // rows), DTM row tiles of 16 targets at most (d <= 16 DTM); sources k = 4 ks + l / 16 in groups
 // of 8 steps whose loads are issued together.
+__device__ __forceinline__ void tile_loads(const unsigned* Rv, int h, int kq, unsigned cb, const char* Vb,
+                                           double (&bop)[8]) {
+#pragma unroll
+  for (int j = 0; j < 8; j++) {
+    const unsigned o = Rv[4 * (8 * h + j) + kq];
+    bop[j] = *reinterpret_cast<const double*>(Vb + ((o & ~1u) + cb));
+  }
+}
+
 template <int DTM>
-__device__ __forceinline__ void tile_product(const PNTileArgs& a, const double* Hs, const unsigned* Rv,
-                                             const unsigned* Rz, const int* Pi, int d, int HW, int c, int kq,
-                                             bool cok, unsigned cb, const char* Vb, char* Zb) {
-  const int KS = (d + 3) >> 2, DT = (d + 15) >> 4;
-  int tb[DTM];
-  d4 acc[DTM];
+__device__ __forceinline__ void tile_mfma(const double* Hs, const unsigned* Rv, const int* Pi, int h, int KS, int DT,
+                                          const int (&tb)[DTM], int kq, const double (&bop)[8], d4 (&acc)[DTM]) {
+#pragma unroll
+  for (int j = 0; j < 8; j++) {
+    if (8 * h + j < KS) {
+      const int kk = 4 * (8 * h + j) + kq;
+      const double b = flip_if(bop[j], Rv[kk] & 1u);
+      const int pk = Pi[kk];
+      double av[DTM];
+#pragma unroll
+      for (int mt = 0; mt < DTM; mt++) av[mt] = Hs[tb[mt] + pk];
+#pragma unroll
+      for (int mt = 0; mt < DTM; mt++)
+        if (mt < DT) acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mt], b, acc[mt], 0, 0, 0);
+    }
+  }
+}
+
+template <int DTM>
+__device__ __forceinline__ void tile_init(const int* Pi, int HW, int c, int (&tb)[DTM], d4 (&acc)[DTM]) {
 #pragma unroll
   for (int mt = 0; mt < DTM; mt++) {
     tb[mt] = Pi[16 * mt + c] * HW;
     acc[mt] = d4{0.0, 0.0, 0.0, 0.0};
   }
-#pragma unroll
-  for (int h = 0; h < DTM / 2; h++) {
-    double bop[8];
-#pragma unroll
-    for (int j = 0; j < 8; j++) {
-      const unsigned o = Rv[4 * (8 * h + j) + kq];
-      bop[j] = flip_if(*reinterpret_cast<const double*>(Vb + ((o & ~1u) + cb)), o & 1u);
-    }
-#pragma unroll
-    for (int j = 0; j < 8; j++) {
-      if (8 * h + j < KS) {
-        const int pk = Pi[4 * (8 * h + j) + kq];
-        double av[DTM];
-#pragma unroll
-        for (int mt = 0; mt < DTM; mt++) av[mt] = Hs[tb[mt] + pk];
-#pragma unroll
-        for (int mt = 0; mt < DTM; mt++)
-          if (mt < DT) acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mt], bop[j], acc[mt], 0, 0, 0);
-      }
-    }
-    __builtin_amdgcn_sched_barrier(0);
-  }
+}
+
+template <int DTM>
+__device__ __forceinline__ void tile_store(const unsigned* Rz, int d, int DT, int c, int kq, bool cok, char* Zb,
+                                           const d4 (&acc)[DTM]) {
   // D: lane l, register v holds target 16 mt + l / 16 + 4 v, column c
 #pragma unroll
   for (int mt = 0; mt < DTM; mt++) {
@@ -108,10 +114,50 @@ __device__ __forceinline__ void tile_product(const PNTileArgs& a, const double* 
       for (int v = 0; v < 4; v++) {
         const int i = 16 * mt + kq + 4 * v;
         const unsigned z = Rz[i];
-        if (i < d && cok) *reinterpret_cast<double*>(Zb + ((z & ~127u) + (unsigned)c * 8u)) = flip_if(acc[mt][v], z & 1u);
+        if (i < d && cok)
+          __builtin_nontemporal_store(flip_if(acc[mt][v], z & 1u),
+                                      reinterpret_cast<double*>(Zb + ((z & ~127u) + (unsigned)c * 8u)));
       }
     }
   }
+}
+
+template <int DTM>
+__device__ __forceinline__ void tile_product(const double* Hs, const unsigned* Rv, const unsigned* Rz, const int* Pi,
+                                             int d, int HW, int c, int kq, bool cok, unsigned cb, const char* Vb,
+                                             char* Zb) {
+  const int KS = (d + 3) >> 2, DT = (d + 15) >> 4;
+  int tb[DTM];
+  d4 acc[DTM];
+  tile_init<DTM>(Pi, HW, c, tb, acc);
+#pragma unroll
+  for (int h = 0; h < DTM / 2; h++) {
+    double bop[8];
+    tile_loads(Rv, h, kq, cb, Vb, bop);
+    tile_mfma<DTM>(Hs, Rv, Pi, h, KS, DT, tb, kq, bop, acc);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  tile_store<DTM>(Rz, d, DT, c, kq, cok, Zb, acc);
+}
+
+// Two core pairs of at most 32 allowed pairs each: the loads of both are issued before the
+// products, so a wavefront keeps twice the rows in flight.
+__device__ __forceinline__ void tile_product2(const double* Hs, const unsigned* RvA, const unsigned* RzA,
+                                              const int* PiA, int dA, const unsigned* RvB, const unsigned* RzB,
+                                              const int* PiB, int dB, int HW, int c, int kq, bool cok, unsigned cb,
+                                              const char* Vb, char* Zb) {
+  const int KSA = (dA + 3) >> 2, DTA = (dA + 15) >> 4, KSB = (dB + 3) >> 2, DTB = (dB + 15) >> 4;
+  double bA[8], bB[8];
+  tile_loads(RvA, 0, kq, cb, Vb, bA);
+  tile_loads(RvB, 0, kq, cb, Vb, bB);
+  int tbA[2], tbB[2];
+  d4 aA[2], aB[2];
+  tile_init<2>(PiA, HW, c, tbA, aA);
+  tile_init<2>(PiB, HW, c, tbB, aB);
+  tile_mfma<2>(Hs, RvA, PiA, 0, KSA, DTA, tbA, kq, bA, aA);
+  tile_store<2>(RzA, dA, DTA, c, kq, cok, Zb, aA);
+  tile_mfma<2>(Hs, RvB, PiB, 0, KSB, DTB, tbB, kq, bB, aB);
+  tile_store<2>(RzB, dB, DTB, c, kq, cok, Zb, aB);
 }
 
 // One work item: a proton core K_p and up to PN_TPB neutron cores of one (2M, parity) group; the
@@ -120,13 +166,13 @@ __device__ __forceinline__ void tile_product(const PNTileArgs& a, const double* 
 // to 64 entries with a valid row and the pair index D2, whose row and column of the staged block
 // are zero, so the products need no masks.
 __global__ __launch_bounds__(256, 4) void pn_tile_kernel(PNTileArgs a) {
-  __shared__ double Hs[(PN_MAXPAIR + 1) * (PN_MAXPAIR + 1)];
+  extern __shared__ __align__(16) double Hs[];  // (widest block + 1)^2 values
   __shared__ int Po[PN_MAXPAIR];  // per pair: offset of its block (-1: no block)
   __shared__ int Pd[PN_MAXPAIR];  // per pair: neutron sector size of its block
   __shared__ int Ps[PN_MAXPAIR];  // per pair: x | u << 8
-  __shared__ unsigned Rv[4][64];
-  __shared__ unsigned Rz[4][64];
-  __shared__ int Pi[4][64];
+  __shared__ unsigned Rv[4][2][64];
+  __shared__ unsigned Rz[4][2][64];
+  __shared__ int Pi[4][2][64];
   const int item = pn_xcd_item(blockIdx.x, a.nitems);
   if (item >= a.nitems) return;
   const int4 it = a.items[item];
@@ -153,39 +199,56 @@ __global__ __launch_bounds__(256, 4) void pn_tile_kernel(PNTileArgs a) {
   const int poff = Po[lp], pdn = Pd[lp];
   const int rp = a.rkp[it.y * a.ns + (xu & 255)];  // the proton core is fixed for the item
   const bool lok = l < D2 && poff >= 0 && rp >= 0;
+  const int bp = rp >> 24;
+  const int rowp = poff + (rp & 0xFFFFFF) * pdn;
   const char* Vb = reinterpret_cast<const char*>(a.V);
   char* Zb = reinterpret_cast<char*>(a.Z);
-  int cn = it.z + w;
-  const int cend = it.z + it.w;
-  int rnn = cn < cend ? a.rkn[cn * a.ns + us] : -1;  // loaded one core pair ahead
-  for (; cn < cend; cn += 4) {
-    const int rn = rnn;
-    if (cn + 4 < cend) rnn = a.rkn[(cn + 4) * a.ns + us];
-    // lane l: pair l of the block, allowed when both states lie outside the cores and the
-    // target's sectors form a block of the space
+  // the list of one core pair (neutron core entry rn) into buffer q; returns its allowed pairs
+  auto list = [&](int rn, int q) __attribute__((always_inline)) {
     const bool ok = lok && rn >= 0;
     const uint64_t mask = __ballot(ok);
     const int d = __popcll(mask);
-    if (d == 0) continue;  // uniform
+    if (d == 0) return 0;  // uniform
     const int below = __popcll(mask & ((1ull << l) - 1));
-    const int bp = rp >> 24, bn = rn >> 24;
-    const int row = poff + (rp & 0xFFFFFF) * pdn + (rn & 0xFFFFFF);
+    const int bn = rn >> 24;
+    const int row = rowp + (rn & 0xFFFFFF);
     const unsigned sg = (unsigned)((bp + bn) & 1);
     const int lead = __builtin_amdgcn_readlane(row, __builtin_ctzll(mask));
     if (ok) {
-      Rv[w][below] = (unsigned)row * (unsigned)a.vrow | sg;
-      Rz[w][below] = ((unsigned)((bp * a.nneut + bn) * a.D + row) << 7) | sg;
-      Pi[w][below] = l;
+      Rv[w][q][below] = (unsigned)row * (unsigned)a.vrow | sg;
+      Rz[w][q][below] = ((unsigned)((bp * a.nneut + bn) * a.D + row) << 7) | sg;
+      Pi[w][q][below] = l;
     } else {  // padding: a valid row, the zero pair
       const int pad = d + l - below;
-      Rv[w][pad] = (unsigned)lead * (unsigned)a.vrow;
-      Pi[w][pad] = D2;
+      Rv[w][q][pad] = (unsigned)lead * (unsigned)a.vrow;
+      Pi[w][q][pad] = D2;
     }
+    return d;
+  };
+  int cn = it.z + w;
+  const int cend = it.z + it.w;
+  // neutron-core entries of the next two core pairs of this wavefront, loaded one step ahead
+  int rnA = cn < cend ? a.rkn[cn * a.ns + us] : -1;
+  int rnB = cn + 4 < cend ? a.rkn[(cn + 4) * a.ns + us] : -1;
+  for (; cn < cend; cn += 8) {
+    const int rA = rnA, rB = rnB;
+    const bool hasB = cn + 4 < cend;
+    if (cn + 8 < cend) rnA = a.rkn[(cn + 8) * a.ns + us];
+    if (cn + 12 < cend) rnB = a.rkn[(cn + 12) * a.ns + us];
+    const int dA = list(rA, 0);
+    const int dB = hasB ? list(rB, 1) : 0;
     // the lists are written and read by this wavefront only: LDS operations of one wavefront
     // complete in order, so only the compiler must keep them in place
     __builtin_amdgcn_wave_barrier();
-    if (d <= 32) tile_product<2>(a, Hs, Rv[w], Rz[w], Pi[w], d, HW, c, kq, cok, cb, Vb, Zb);
-    else tile_product<4>(a, Hs, Rv[w], Rz[w], Pi[w], d, HW, c, kq, cok, cb, Vb, Zb);
+    if (dA > 0 && dA <= 32 && dB > 0 && dB <= 32) {
+      tile_product2(Hs, Rv[w][0], Rz[w][0], Pi[w][0], dA, Rv[w][1], Rz[w][1], Pi[w][1], dB, HW, c, kq, cok, cb, Vb,
+                    Zb);
+    } else {
+      if (dA > 32) tile_product<4>(Hs, Rv[w][0], Rz[w][0], Pi[w][0], dA, HW, c, kq, cok, cb, Vb, Zb);
+      else if (dA > 0) tile_product<2>(Hs, Rv[w][0], Rz[w][0], Pi[w][0], dA, HW, c, kq, cok, cb, Vb, Zb);
+      if (dB > 32) tile_product<4>(Hs, Rv[w][1], Rz[w][1], Pi[w][1], dB, HW, c, kq, cok, cb, Vb, Zb);
+      else if (dB > 0) tile_product<2>(Hs, Rv[w][1], Rz[w][1], Pi[w][1], dB, HW, c, kq, cok, cb, Vb, Zb);
+    }
     __builtin_amdgcn_wave_barrier();
   }
 }
@@ -199,7 +262,7 @@ __global__ void pn_reduce_kernel(const double* __restrict__ Z, int S, int64_t D,
     if (c >= cval) continue;
     const int64_t t = e >> 4;
     double s = 0.0;
-    for (int k = 0; k < S; k++) s += Z[((int64_t)k * D + t) * 16 + c];
+    for (int k = 0; k < S; k++) s += __builtin_nontemporal_load(Z + ((int64_t)k * D + t) * 16 + c);
     W[t * ldw + c0 + c] += s;
   }
 }
@@ -337,7 +400,10 @@ void build_pn_tiles(Model& m) {
       rblk.insert(rblk.end(), pb.begin(), pb.end());
     }
   if (rect.empty()) return;
-  // work items: per proton core, per neutron group with a rectangle, up to PN_TPB neutron cores
+  // work items: per proton core, per neutron group with a rectangle, up to `chunk` neutron cores
+  // (TRBL_PN_CHUNK: a tuning override)
+  int chunk = PN_TPB;
+  if (const char* ev = std::getenv("TRBL_PN_CHUNK")) chunk = std::max(8, std::min(PN_TPB, std::atoi(ev)));
   std::vector<int> items;
   const int ngn = (int)groups[1].size();
   for (int ip = 0; ip < (int)groups[0].size(); ip++)
@@ -346,8 +412,8 @@ void build_pn_tiles(Model& m) {
         const int r = rect_of[ip * ngn + in];
         if (r < 0) continue;
         const Group& gn = groups[1][in];
-        for (int c0 = 0; c0 < gn.count; c0 += PN_TPB)
-          items.insert(items.end(), {r, cp, gn.start + c0, std::min(PN_TPB, gn.count - c0)});
+        for (int c0 = 0; c0 < gn.count; c0 += chunk)
+          items.insert(items.end(), {r, cp, gn.start + c0, std::min(chunk, gn.count - c0)});
       }
   TRBL_REQUIRE(items.size() / 4 < ((size_t)1 << 31) / 256, TRBL_E_INVALID, "too many core pairs for one launch");
   // the slot buffer: S slots of 16 FP64 columns per basis state, sized within a quarter of the
@@ -386,7 +452,8 @@ void build_pn_tiles(Model& m) {
   T.on = true;
 }
 
-void launch_pn_tiles(const Model& m, int nb, const double* V, int64_t ldv, double* W, int64_t ldw, hipStream_t s) {
+void launch_pn_tiles(const Model& m, int nb, const double* V, int64_t ldv, double* W, int64_t ldw, hipStream_t s,
+                     bool reduce) {
   const PNTiles& T = m.pn;
   PNTileArgs a{};
   a.V = V;
@@ -408,12 +475,15 @@ void launch_pn_tiles(const Model& m, int nb, const double* V, int64_t ldv, doubl
   a.items = T.item0.as<int4>();
   a.nitems = (int)T.items;
   const unsigned grid = (unsigned)((T.items + 7) / 8 * 8);
+  // a wider product reuses the slot buffer per 16 columns, each tile summed into W in turn; with
+  // reduce false (one tile) the own-row kernel sums it
   for (int c0 = 0; c0 < nb; c0 += 16) {
     a.c0 = c0;
     a.cval = std::min(16, nb - c0);
-    hipLaunchKernelGGL(pn_tile_kernel, dim3(grid), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(pn_reduce_kernel, dim3(elementwise_grid(m.dim * 16)), dim3(256), 0, s, (const double*)a.Z, T.S,
-                       m.dim, W, ldw, c0, a.cval);
+    hipLaunchKernelGGL(pn_tile_kernel, dim3(grid), dim3(256), (size_t)(T.max_pairs + 1) * (T.max_pairs + 1) * 8, s, a);
+    if (reduce || c0 + 16 < nb)
+      hipLaunchKernelGGL(pn_reduce_kernel, dim3(elementwise_grid(m.dim * 16)), dim3(256), 0, s, (const double*)a.Z,
+                         T.S, m.dim, W, ldw, c0, a.cval);
   }
   TRBL_HIP(hipGetLastError());
 }
