@@ -88,7 +88,7 @@ def stored_nnz(name):
     return None
 
 
-HV_SOURCES = ("hv.hip", "hv_kern.h", "hv_f64.hip", "hv_f32.hip")
+HV_SOURCES = ("hv.hip", "hv_kern.h", "hv_f64.hip", "hv_f32.hip", "pntile.hip")
 
 
 def hv_source_digest():
@@ -447,7 +447,9 @@ def main():
                 "frac": flops / hv_launch / 1e12 / PEAK_FP64_TFLOPS, "traffic": traffic,
                 "kernel": ("block H.V, FP64: fly_kernel (single species, generated per element) + two row permutations"
                            if (w.n_prot == 0) != (w.n_neut == 0) and D > 2048 else
-                           "block H.V, FP64: hv_rows_kernel (one launch per sector-width bin) + hv_cols_kernel"),
+                           "block H.V, FP64: pn_tile_kernel (proton-neutron part, core-pair blocks on the matrix "
+                           "cores) + hv_own_kernel (neutron-neutron part and slot sum, one launch per sector-width bin) "
+                           "+ hv_cols_kernel (proton-proton part)"),
                 "measured_GBs": (traffic / hv_launch / 1e9) if traffic else None,
                 "per_launch": {"elements": nnz, "flops": flops, "compulsory_bytes": bytes_min,
                                "avg_duration_s": hv_launch}}
