@@ -2,7 +2,9 @@
 import numpy as np
 import pytest
 
-from gpu_common import fp32_bound, fp64_bound, pair, say
+import os
+
+from gpu_common import fp32_bound, fp64_bound, pair, say, term_bound
 from workloads import PF_ORBITS, SD_ORBITS, SD_SPE, PF_SPE, WORKLOADS, random_block, random_tbme
 
 torch = pytest.importorskip("torch")
@@ -37,7 +39,8 @@ def test_apply_matches_dense_oracle(case):
     nnz = int(np.max(np.count_nonzero(H, axis=1)))
     V = random_block(100 + seed, o.dim, nb)
     ref = H @ V
-    bound = fp64_bound(np.abs(H) @ np.abs(V), nnz)
+    # per-term bound: the FP64 product sums the pn terms of each core pair unmerged
+    bound = term_bound(o, np.arange(o.dim), V)
     W = g.apply(torch.from_numpy(V).cuda()).cpu().numpy()
     assert np.all(np.abs(W - ref) <= bound), np.max(np.abs(W - ref) / bound)
     # mixed precision: FP32 vectors, FP32 coefficients, FP32 accumulation
@@ -46,6 +49,47 @@ def test_apply_matches_dense_oracle(case):
     W32 = g.apply(torch.from_numpy(V32).cuda()).cpu().numpy().astype(np.float64)
     b32 = fp32_bound(np.abs(H) @ np.abs(V32.astype(np.float64)), nnz)
     assert np.all(np.abs(W32 - ref32) <= b32), np.max(np.abs(W32 - ref32) / b32)
+
+
+PATH_CASES = [
+    # name, orbits, Z, N, 2M, parity, seed, nb: the FP64 pn part by core-pair blocks (one 16-column
+    # tile summed by the own-row kernel, several tiles, narrower tiles) against the jump-list kernel
+    ("pf22_nb16", PF_ORBITS, 2, 2, 0, 0, 4, 16),
+    ("pf31_nb40", PF_ORBITS, 3, 1, 0, 0, 5, 40),
+    ("sd32_odd_nb5", SD_ORBITS, 3, 2, 1, 0, 2, 5),
+    ("mixpar_neg_nb12", MIXED_PAR, 2, 1, 1, -1, 7, 12),
+]
+
+
+@pytest.mark.parametrize("case", PATH_CASES, ids=lambda c: c[0])
+def test_pair_blocks_match_jump_lists(case):
+    """The two FP64 pn kernels (pair blocks on the matrix cores, and the jump-list rows kernel
+    selected with TRBL_PN_TILES=0 at set-up) agree within the sum of their rounding bounds, and
+    each matches the oracle."""
+    name, orbits, z, n, twoM, par, seed, nb = case
+    say("case", name)
+    tb = random_tbme(orbits, seed)
+    spe = [(-1.5 + 0.7 * k) for k in range(len(orbits))]
+    g, o = pair(orbits, z, n, twoM, tb, spe, spe, par)
+    old = os.environ.get("TRBL_PN_TILES")
+    os.environ["TRBL_PN_TILES"] = "0"
+    try:
+        g0, _ = pair(orbits, z, n, twoM, tb, spe, spe, par, oracle=False)
+    finally:
+        if old is None:
+            del os.environ["TRBL_PN_TILES"]
+        else:
+            os.environ["TRBL_PN_TILES"] = old
+    V = random_block(300 + seed, o.dim, nb)
+    Vt = torch.from_numpy(V).cuda()
+    W1 = g.apply(Vt).cpu().numpy()
+    W0 = g0.apply(Vt).cpu().numpy()
+    idx = np.arange(o.dim)
+    bound = term_bound(o, idx, V)
+    ref = o.apply_rows(V, idx)
+    assert np.all(np.abs(W1 - ref) <= bound)
+    assert np.all(np.abs(W0 - ref) <= bound)
+    assert np.all(np.abs(W1 - W0) <= 2 * bound)
 
 
 def test_apply_deterministic_and_linear():
@@ -72,12 +116,8 @@ def test_apply_full_size_sampled_rows(wname, nrows):
     idx = np.unique(np.concatenate([rng.choice(g.dim, nrows, replace=False), [0, g.dim - 1]]))
     ref = o.apply_rows(V, idx)
     ptr, col, val = o.rows(idx)
-    absHV = np.zeros_like(ref)
-    for r in range(len(idx)):
-        sl = slice(ptr[r], ptr[r + 1])
-        absHV[r] = np.abs(val[sl]) @ np.abs(V[col[sl]])
     nnz = int(np.max(np.diff(ptr)))
-    assert np.all(np.abs(W[idx] - ref) <= fp64_bound(absHV, nnz))
+    assert np.all(np.abs(W[idx] - ref) <= term_bound(o, idx, V))
     # FP32 path on the same rows
     V32 = V.astype(np.float32)
     W32 = g.apply(torch.from_numpy(V32).cuda()).cpu().numpy().astype(np.float64)
