@@ -186,30 +186,23 @@ static void run_hv(const Model& m, int nb, const void* V, int64_t ldv, void* W, 
   a.ntile = P.ntile;
   a.dma = a.dma && nb % P.C == 0;
   a.citem0 = P.citem0.as<int64_t>();
-  // FP64 with the pair-block tables: the rows and columns kernels write the identical-particle
-  // parts, the pair blocks add the pn part
-  bool own = false;
-  if constexpr (sizeof(T) == 8) {
-    own = m.pn.on && (double)m.dim * (double)ldv * 8.0 < 4294967296.0;  // 32-bit byte offsets into V
-    for (const auto& B : P.bins) own = own && B->mp == 1;
-  }
+  // with the pair-block tables the rows and columns kernels write the identical-particle parts and
+  // the pair blocks add the pn part
+  bool own = m.pn.on && (double)m.dim * (double)ldv * sizeof(T) < 4294967296.0;  // 32-bit byte offsets into V
+  for (const auto& B : P.bins) own = own && B->mp == 1;
   a.own = own ? 1 : 0;
   // the pn part goes to the slot buffer; when one 16-column tile covers the product it is written
   // first and the own-row kernel sums it into W, else it is added by its own pass after the
   // identical-particle parts
   const bool fused = own && P.C == 16 && nb <= 16;
-  if constexpr (sizeof(T) == 8) {
-    if (fused) {
-      launch_pn_tiles(m, nb, static_cast<const double*>(V), ldv, static_cast<double*>(W), ldw, s, false);
-      a.zs = m.pn.S;
-      a.zstride = m.dim * 16;
-      a.zbuf = m.pn.z.as<double>();
-    }
+  if (fused) {
+    launch_pn_tiles<T>(m, nb, static_cast<const T*>(V), ldv, static_cast<T*>(W), ldw, s, false);
+    a.zs = m.pn.S;
+    a.zstride = m.dim * 16;
+    a.zbuf = m.pn.z.p;
   }
   dispatch_hv<T>(a, P, s);
-  if constexpr (sizeof(T) == 8) {
-    if (own && !fused) launch_pn_tiles(m, nb, static_cast<const double*>(V), ldv, static_cast<double*>(W), ldw, s, true);
-  }
+  if (own && !fused) launch_pn_tiles<T>(m, nb, static_cast<const T*>(V), ldv, static_cast<T*>(W), ldw, s, true);
 }
 
 void prepare_hv_plans(const Model& m, int precision, const int* widths, int n) {

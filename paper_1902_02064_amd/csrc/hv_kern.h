@@ -43,8 +43,8 @@ struct HVArgs {
   int dma;               // source rows copied by global->LDS DMA (16-byte aligned rows)
   int own;               // identical-particle parts only (the pn part is added by the pair blocks)
   int zs;                // own-row kernel: slots of the pair-block buffer summed into W (0: none)
-  int64_t zstride;       // elements between slots of that buffer ([slot][D][16] FP64)
-  const double* zbuf;
+  int64_t zstride;       // elements between slots of that buffer ([slot][D][16] values of type T)
+  const void* zbuf;
   int64_t nn_total;
   const int* blk_dp;
   const int* blk_dn;
@@ -591,7 +591,7 @@ __global__ __launch_bounds__(NTB) void hv_own_kernel(HVArgs<T> a) {
 #pragma unroll
     for (int u = 0; u < 4; u++) gather_row<T, C>(acc, vv[u], B0, cc[u] * L::RB);
   }
-  if constexpr (sizeof(T) == 8 && C == 16) {
+  if constexpr (C == 16) {
     if (a.zs > 0) {
       // the pn part from the pair-block slots: park the rows in LDS (target order), then stream the
       // slots of the proton row's dn targets in address order and write W once
@@ -599,37 +599,33 @@ __global__ __launch_bounds__(NTB) void hv_own_kernel(HVArgs<T> a) {
       if (live) {
         const int tg = a.nlane[gn0 + ln];
 #pragma unroll
-        for (int t = 0; t < L::CPR; t++)
-          *reinterpret_cast<RowChunk<T>*>(B0 + L::at(tg, t ^ L::rot())) = RowChunk<T>{acc[2 * t], acc[2 * t + 1]};
+        for (int t = 0; t < L::CPR; t++) {
+          T* d = reinterpret_cast<T*>(B0 + L::at(tg, t ^ L::rot()));
+#pragma unroll
+          for (int v = 0; v < L::VPC; v++) d[v] = acc[t * L::VPC + v];
+        }
       }
       __syncthreads();
+      typedef T zv __attribute__((ext_vector_type(L::VPC)));  // one 16-byte chunk
       const int64_t r0 = off + (int64_t)pl * dn;
       const int lo_t = tlo, hi_t = min(dn, tlo + nthr);
       for (int e = lo_t * L::CPR + tid; e < hi_t * L::CPR; e += nthr) {
         const int t = e / L::CPR, k = e % L::CPR;
-        double2 v = *reinterpret_cast<const double2*>(B0 + L::at(t, k));
-        const double* z = a.zbuf + (r0 + t) * 16 + 2 * k;
-        typedef double dv2 __attribute__((ext_vector_type(2)));
+        zv v = *reinterpret_cast<const zv*>(B0 + L::at(t, k));
+        const T* z = static_cast<const T*>(a.zbuf) + (r0 + t) * 16 + L::VPC * k;
         int q = 0;
         for (; q + 8 <= a.zs; q += 8) {  // eight slots in flight, summed in slot order
-          dv2 zq[8];
+          zv zq[8];
 #pragma unroll
-          for (int j = 0; j < 8; j++)
-            zq[j] = __builtin_nontemporal_load(reinterpret_cast<const dv2*>(z + (q + j) * a.zstride));
+          for (int j = 0; j < 8; j++) zq[j] = __builtin_nontemporal_load(reinterpret_cast<const zv*>(z + (q + j) * a.zstride));
 #pragma unroll
-          for (int j = 0; j < 8; j++) {
-            v.x += zq[j].x;
-            v.y += zq[j].y;
-          }
+          for (int j = 0; j < 8; j++) v += zq[j];
         }
-        for (; q < a.zs; q++) {
-          const dv2 zq = __builtin_nontemporal_load(reinterpret_cast<const dv2*>(z + q * a.zstride));
-          v.x += zq.x;
-          v.y += zq.y;
-        }
-        T* w = a.W + (r0 + t) * a.ldw + c0 + 2 * k;
-        if (2 * k < cvalid) w[0] = v.x;
-        if (2 * k + 1 < cvalid) w[1] = v.y;
+        for (; q < a.zs; q++) v += __builtin_nontemporal_load(reinterpret_cast<const zv*>(z + q * a.zstride));
+        T* w = a.W + (r0 + t) * a.ldw + c0 + L::VPC * k;
+#pragma unroll
+        for (int j = 0; j < L::VPC; j++)
+          if (L::VPC * k + j < cvalid) w[j] = v[j];
       }
       return;
     }
@@ -738,14 +734,12 @@ static void dispatch_c(HVArgs<T>& a, const HVPlan& P, hipStream_t s) {
     a.bin_blocks = B.blocks.as<int>();
     a.bin_item0 = B.item0.as<int64_t>();
     a.bin_nblk = B.nblk;
-    if constexpr (sizeof(T) == 8) {
-      if (a.own) {
-        TRBL_REQUIRE(B.mp == 1, TRBL_E_INVALID, "own-row plan with several targets per lane");
-        if (B.ntb == 256) launch_own<T, C, 256>(a, B, s);
-        else if (B.ntb == 768) launch_own<T, C, 768>(a, B, s);
-        else launch_own<T, C, 1024>(a, B, s);
-        continue;
-      }
+    if (a.own) {
+      TRBL_REQUIRE(B.mp == 1, TRBL_E_INVALID, "own-row plan with several targets per lane");
+      if (B.ntb == 256) launch_own<T, C, 256>(a, B, s);
+      else if (B.ntb == 768) launch_own<T, C, 768>(a, B, s);
+      else launch_own<T, C, 1024>(a, B, s);
+      continue;
     }
 #define TRBL_ROWS_RB(NTB)                                                   \
   (B.rb_kb == 24   ? launch_rows<T, C, NTB, 24>(a, B, s)                    \

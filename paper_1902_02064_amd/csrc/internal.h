@@ -165,11 +165,11 @@ struct PNTiles {
   int64_t items = 0;         // workgroups of one launch
   DevBuf cw[2], rk[2];       // core words; [core * ns + state]: position of state << 24 | local index of core + state, -1 inside
   DevBuf pr_off, pr_xu;      // pair blocks: x | u << 8
-  DevBuf hb_off, hb;         // per pair block: D2 x D2 FP64 matrix, row = target pair
+  DevBuf hb_off, hb, hb32;   // per pair block: D2 x D2 matrix (FP64, FP32), row = target pair
   DevBuf rect, rblk, item0;  // rectangles (pair block, rblk start), per rectangle and pair the target block
                              // (-1: none), work items (rectangle, proton core, first neutron core, count)
   DevBuf boff;               // block offsets as 32-bit integers
-  DevBuf z;                  // slot buffer [S][D][16] of one 16-column tile
+  DevBuf z;                  // slot buffer [S][D][16] of one 16-column tile (FP64, or FP32 in its first half)
 };
 
 struct MTerm {  // m-scheme two-body term c+_a c+_b c_d c_c (species-local state indices)
@@ -215,7 +215,7 @@ struct Model {
   int fly_s = 1;     // the occupied species
   int fly_half = 0;  // m-states in the low part of the two-level ranking
   mutable DevBuf fly_buf[2];  // V and W in the internal order (FP32, FP64)
-  mutable PNTiles pn;         // FP64 pn part as dense pair blocks (when its slot buffer fits)
+  mutable PNTiles pn;         // pn part as dense pair blocks (when its slot buffer fits)
 };
 
 // host helpers (model.cpp)
@@ -233,8 +233,8 @@ double clebsch(int tj1, int tm1, int tj2, int tm2, int tJ, int tM);
 // the pn part of H V to W (FP64, W already holding the identical-particle parts)
 void build_pn_tiles(Model& m);
 // (reduce false: the last 16-column tile stays in the slot buffer for the own-row kernel to sum)
-void launch_pn_tiles(const Model& m, int nb, const double* V, int64_t ldv, double* W, int64_t ldw, hipStream_t s,
-                     bool reduce);
+template <class T>
+void launch_pn_tiles(const Model& m, int nb, const T* V, int64_t ldv, T* W, int64_t ldw, hipStream_t s, bool reduce);
 
 // device launchers (hv.hip)
 void launch_apply(const Model& m, int precision, int nb, const void* V, int64_t ldv, void* W, int64_t ldw,

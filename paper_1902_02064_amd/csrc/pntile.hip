@@ -29,14 +29,36 @@ namespace trbl {
 
 namespace {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
+// Per precision: the matrix-core accumulator, the instruction, and the row of its output a lane
+// register holds (measured on gfx950: FP64 D[l / 16 + 4 v][l % 16], FP32 D[4 (l / 16) + v][l % 16]).
+template <class T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef double acc __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc run(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kq, int v) { return kq + 4 * v; }
+  static constexpr unsigned ZSHIFT = 7;  // bytes of a 16-value row: 128
+};
+template <>
+struct Mfma<float> {
+  typedef float acc __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc run(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kq, int v) { return 4 * kq + v; }
+  static constexpr unsigned ZSHIFT = 6;  // 64
+};
 
 constexpr int PN_TPB = 256;       // most core pairs of one work item
 constexpr int PN_MAXPAIR = 64;    // widest pair block (one ballot)
 
+template <class T>
 struct PNTileArgs {
-  const double* V;
-  double* Z;
+  const T* V;
+  T* Z;
   int c0, cval;  // column tile: first column, valid columns (<= 16)
   int ns, nneut, D, vrow;  // vrow: bytes per row of V
   const int* rkp;  // [core * ns + state]: position << 24 | local index of core + state, -1 inside
@@ -46,7 +68,7 @@ struct PNTileArgs {
   const int* pr_off;
   const int* pr_xu;
   const int* hb_off;
-  const double* hb;
+  const T* hb;
   const int* rect;    // per rectangle: pair block, first entry of its list in rblk
   const int* rblk;    // per rectangle and pair: block of the target's sectors, -1 if none
   const int4* items;  // per work item: rectangle, proton core, first neutron core, count
@@ -62,102 +84,104 @@ __device__ __forceinline__ int pn_xcd_item(int bid, int n) {
 __device__ __forceinline__ double flip_if(double x, unsigned s) {
   return __hiloint2double(__double2hiint(x) ^ (int)(s << 31), __double2loint(x));
 }
+__device__ __forceinline__ float flip_if(float x, unsigned s) { return __int_as_float(__float_as_int(x) ^ (int)(s << 31)); }
 
 // The product of one core pair: Z rows of its d allowed targets = (staged block) x (signed source
 // rows), DTM row tiles of 16 targets at most (d <= 16 DTM); sources k = 4 ks + l / 16 in groups
 // of 8 steps whose loads are issued together.
+template <class T>
 __device__ __forceinline__ void tile_loads(const unsigned* Rv, int h, int kq, unsigned cb, const char* Vb,
-                                           double (&bop)[8]) {
+                                           T (&bop)[8]) {
 #pragma unroll
   for (int j = 0; j < 8; j++) {
     const unsigned o = Rv[4 * (8 * h + j) + kq];
-    bop[j] = *reinterpret_cast<const double*>(Vb + ((o & ~1u) + cb));
+    bop[j] = *reinterpret_cast<const T*>(Vb + ((o & ~1u) + cb));
   }
 }
 
-template <int DTM>
-__device__ __forceinline__ void tile_mfma(const double* Hs, const unsigned* Rv, const int* Pi, int h, int KS, int DT,
-                                          const int (&tb)[DTM], int kq, const double (&bop)[8], d4 (&acc)[DTM]) {
+template <class T, int DTM>
+__device__ __forceinline__ void tile_mfma(const T* Hs, const unsigned* Rv, const int* Pi, int h, int KS, int DT,
+                                          const int (&tb)[DTM], int kq, const T (&bop)[8],
+                                          typename Mfma<T>::acc (&acc)[DTM]) {
 #pragma unroll
   for (int j = 0; j < 8; j++) {
     if (8 * h + j < KS) {
       const int kk = 4 * (8 * h + j) + kq;
-      const double b = flip_if(bop[j], Rv[kk] & 1u);
+      const T b = flip_if(bop[j], Rv[kk] & 1u);
       const int pk = Pi[kk];
-      double av[DTM];
+      T av[DTM];
 #pragma unroll
       for (int mt = 0; mt < DTM; mt++) av[mt] = Hs[tb[mt] + pk];
 #pragma unroll
       for (int mt = 0; mt < DTM; mt++)
-        if (mt < DT) acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mt], b, acc[mt], 0, 0, 0);
+        if (mt < DT) acc[mt] = Mfma<T>::run(av[mt], b, acc[mt]);
     }
   }
 }
 
-template <int DTM>
-__device__ __forceinline__ void tile_init(const int* Pi, int HW, int c, int (&tb)[DTM], d4 (&acc)[DTM]) {
+template <class T, int DTM>
+__device__ __forceinline__ void tile_init(const int* Pi, int HW, int c, int (&tb)[DTM],
+                                          typename Mfma<T>::acc (&acc)[DTM]) {
 #pragma unroll
   for (int mt = 0; mt < DTM; mt++) {
     tb[mt] = Pi[16 * mt + c] * HW;
-    acc[mt] = d4{0.0, 0.0, 0.0, 0.0};
+    acc[mt] = typename Mfma<T>::acc{0, 0, 0, 0};
   }
 }
 
-template <int DTM>
+template <class T, int DTM>
 __device__ __forceinline__ void tile_store(const unsigned* Rz, int d, int DT, int c, int kq, bool cok, char* Zb,
-                                           const d4 (&acc)[DTM]) {
-  // D: lane l, register v holds target 16 mt + l / 16 + 4 v, column c
+                                           const typename Mfma<T>::acc (&acc)[DTM]) {
 #pragma unroll
   for (int mt = 0; mt < DTM; mt++) {
     if (mt < DT) {
 #pragma unroll
       for (int v = 0; v < 4; v++) {
-        const int i = 16 * mt + kq + 4 * v;
+        const int i = 16 * mt + Mfma<T>::row(kq, v);
         const unsigned z = Rz[i];
         if (i < d && cok)
-          __builtin_nontemporal_store(flip_if(acc[mt][v], z & 1u),
-                                      reinterpret_cast<double*>(Zb + ((z & ~127u) + (unsigned)c * 8u)));
+          __builtin_nontemporal_store(flip_if((T)acc[mt][v], z & 1u),
+                                      reinterpret_cast<T*>(Zb + ((z & ~63u) + (unsigned)c * (unsigned)sizeof(T))));
       }
     }
   }
 }
 
-template <int DTM>
-__device__ __forceinline__ void tile_product(const double* Hs, const unsigned* Rv, const unsigned* Rz, const int* Pi,
-                                             int d, int HW, int c, int kq, bool cok, unsigned cb, const char* Vb,
-                                             char* Zb) {
+template <class T, int DTM>
+__device__ __forceinline__ void tile_product(const T* Hs, const unsigned* Rv, const unsigned* Rz, const int* Pi, int d,
+                                             int HW, int c, int kq, bool cok, unsigned cb, const char* Vb, char* Zb) {
   const int KS = (d + 3) >> 2, DT = (d + 15) >> 4;
   int tb[DTM];
-  d4 acc[DTM];
-  tile_init<DTM>(Pi, HW, c, tb, acc);
+  typename Mfma<T>::acc acc[DTM];
+  tile_init<T, DTM>(Pi, HW, c, tb, acc);
 #pragma unroll
   for (int h = 0; h < DTM / 2; h++) {
-    double bop[8];
-    tile_loads(Rv, h, kq, cb, Vb, bop);
-    tile_mfma<DTM>(Hs, Rv, Pi, h, KS, DT, tb, kq, bop, acc);
+    T bop[8];
+    tile_loads<T>(Rv, h, kq, cb, Vb, bop);
+    tile_mfma<T, DTM>(Hs, Rv, Pi, h, KS, DT, tb, kq, bop, acc);
     __builtin_amdgcn_sched_barrier(0);
   }
-  tile_store<DTM>(Rz, d, DT, c, kq, cok, Zb, acc);
+  tile_store<T, DTM>(Rz, d, DT, c, kq, cok, Zb, acc);
 }
 
 // Two core pairs of at most 32 allowed pairs each: the loads of both are issued before the
 // products, so a wavefront keeps twice the rows in flight.
-__device__ __forceinline__ void tile_product2(const double* Hs, const unsigned* RvA, const unsigned* RzA,
-                                              const int* PiA, int dA, const unsigned* RvB, const unsigned* RzB,
-                                              const int* PiB, int dB, int HW, int c, int kq, bool cok, unsigned cb,
-                                              const char* Vb, char* Zb) {
+template <class T>
+__device__ __forceinline__ void tile_product2(const T* Hs, const unsigned* RvA, const unsigned* RzA, const int* PiA,
+                                              int dA, const unsigned* RvB, const unsigned* RzB, const int* PiB, int dB,
+                                              int HW, int c, int kq, bool cok, unsigned cb, const char* Vb, char* Zb) {
   const int KSA = (dA + 3) >> 2, DTA = (dA + 15) >> 4, KSB = (dB + 3) >> 2, DTB = (dB + 15) >> 4;
-  double bA[8], bB[8];
-  tile_loads(RvA, 0, kq, cb, Vb, bA);
-  tile_loads(RvB, 0, kq, cb, Vb, bB);
+  T bA[8], bB[8];
+  tile_loads<T>(RvA, 0, kq, cb, Vb, bA);
+  tile_loads<T>(RvB, 0, kq, cb, Vb, bB);
   int tbA[2], tbB[2];
-  d4 aA[2], aB[2];
-  tile_init<2>(PiA, HW, c, tbA, aA);
-  tile_init<2>(PiB, HW, c, tbB, aB);
-  tile_mfma<2>(Hs, RvA, PiA, 0, KSA, DTA, tbA, kq, bA, aA);
-  tile_store<2>(RzA, dA, DTA, c, kq, cok, Zb, aA);
-  tile_mfma<2>(Hs, RvB, PiB, 0, KSB, DTB, tbB, kq, bB, aB);
-  tile_store<2>(RzB, dB, DTB, c, kq, cok, Zb, aB);
+  typename Mfma<T>::acc aA[2], aB[2];
+  tile_init<T, 2>(PiA, HW, c, tbA, aA);
+  tile_init<T, 2>(PiB, HW, c, tbB, aB);
+  tile_mfma<T, 2>(Hs, RvA, PiA, 0, KSA, DTA, tbA, kq, bA, aA);
+  tile_store<T, 2>(RzA, dA, DTA, c, kq, cok, Zb, aA);
+  tile_mfma<T, 2>(Hs, RvB, PiB, 0, KSB, DTB, tbB, kq, bB, aB);
+  tile_store<T, 2>(RzB, dB, DTB, c, kq, cok, Zb, aB);
 }
 
 // One work item: a proton core K_p and up to PN_TPB neutron cores of one (2M, parity) group; the
@@ -165,8 +189,10 @@ __device__ __forceinline__ void tile_product2(const double* Hs, const unsigned* 
 // (V byte offset | source sign, slot byte offset | target sign, pair index); the list is padded
 // to 64 entries with a valid row and the pair index D2, whose row and column of the staged block
 // are zero, so the products need no masks.
-__global__ __launch_bounds__(256, 4) void pn_tile_kernel(PNTileArgs a) {
-  extern __shared__ __align__(16) double Hs[];  // (widest block + 1)^2 values
+template <class T>
+__global__ __launch_bounds__(256, 4) void pn_tile_kernel(PNTileArgs<T> a) {
+  extern __shared__ __align__(16) char hs_[];  // (widest block + 1)^2 values
+  T* Hs = reinterpret_cast<T*>(hs_);
   __shared__ int Po[PN_MAXPAIR];  // per pair: offset of its block (-1: no block)
   __shared__ int Pd[PN_MAXPAIR];  // per pair: neutron sector size of its block
   __shared__ int Ps[PN_MAXPAIR];  // per pair: x | u << 8
@@ -178,11 +204,9 @@ __global__ __launch_bounds__(256, 4) void pn_tile_kernel(PNTileArgs a) {
   const int4 it = a.items[item];
   const int k = a.rect[2 * it.x], rb0 = a.rect[2 * it.x + 1];
   const int q0 = a.pr_off[k], D2 = a.pr_off[k + 1] - q0, HW = D2 + 1;
-  const double* hg = a.hb + a.hb_off[k];
-  for (int e = threadIdx.x; e < HW * HW; e += 256) {
-    const int i = e / HW, j = e - i * HW;
-    Hs[e] = (i < D2 && j < D2) ? hg[i * D2 + j] : 0.0;
-  }
+  const T* hg = a.hb + a.hb_off[k];
+  for (int i = threadIdx.x / 64; i < HW; i += 4)
+    for (int j = threadIdx.x % 64; j < HW; j += 64) Hs[i * HW + j] = (i < D2 && j < D2) ? hg[i * D2 + j] : T(0);
   for (int e = threadIdx.x; e < D2; e += 256) {
     Ps[e] = a.pr_xu[q0 + e];
     const int b = a.rblk[rb0 + e];
@@ -193,7 +217,8 @@ __global__ __launch_bounds__(256, 4) void pn_tile_kernel(PNTileArgs a) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int c = l & 15, kq = l >> 4;
   const bool cok = c < a.cval;
-  const unsigned cb = (unsigned)(a.c0 + min(c, a.cval - 1)) * 8u;  // column byte; beyond the tile: a valid column
+  // column byte; beyond the tile: a valid column
+  const unsigned cb = (unsigned)(a.c0 + min(c, a.cval - 1)) * (unsigned)sizeof(T);
   const int lp = min(l, D2 - 1);
   const int xu = Ps[lp], us = xu >> 8;
   const int poff = Po[lp], pdn = Pd[lp];
@@ -216,7 +241,7 @@ __global__ __launch_bounds__(256, 4) void pn_tile_kernel(PNTileArgs a) {
     const int lead = __builtin_amdgcn_readlane(row, __builtin_ctzll(mask));
     if (ok) {
       Rv[w][q][below] = (unsigned)row * (unsigned)a.vrow | sg;
-      Rz[w][q][below] = ((unsigned)((bp * a.nneut + bn) * a.D + row) << 7) | sg;
+      Rz[w][q][below] = ((unsigned)((bp * a.nneut + bn) * a.D + row) << Mfma<T>::ZSHIFT) | sg;
       Pi[w][q][below] = l;
     } else {  // padding: a valid row, the zero pair
       const int pad = d + l - below;
@@ -241,27 +266,28 @@ __global__ __launch_bounds__(256, 4) void pn_tile_kernel(PNTileArgs a) {
     // complete in order, so only the compiler must keep them in place
     __builtin_amdgcn_wave_barrier();
     if (dA > 0 && dA <= 32 && dB > 0 && dB <= 32) {
-      tile_product2(Hs, Rv[w][0], Rz[w][0], Pi[w][0], dA, Rv[w][1], Rz[w][1], Pi[w][1], dB, HW, c, kq, cok, cb, Vb,
-                    Zb);
+      tile_product2<T>(Hs, Rv[w][0], Rz[w][0], Pi[w][0], dA, Rv[w][1], Rz[w][1], Pi[w][1], dB, HW, c, kq, cok, cb, Vb,
+                       Zb);
     } else {
-      if (dA > 32) tile_product<4>(Hs, Rv[w][0], Rz[w][0], Pi[w][0], dA, HW, c, kq, cok, cb, Vb, Zb);
-      else if (dA > 0) tile_product<2>(Hs, Rv[w][0], Rz[w][0], Pi[w][0], dA, HW, c, kq, cok, cb, Vb, Zb);
-      if (dB > 32) tile_product<4>(Hs, Rv[w][1], Rz[w][1], Pi[w][1], dB, HW, c, kq, cok, cb, Vb, Zb);
-      else if (dB > 0) tile_product<2>(Hs, Rv[w][1], Rz[w][1], Pi[w][1], dB, HW, c, kq, cok, cb, Vb, Zb);
+      if (dA > 32) tile_product<T, 4>(Hs, Rv[w][0], Rz[w][0], Pi[w][0], dA, HW, c, kq, cok, cb, Vb, Zb);
+      else if (dA > 0) tile_product<T, 2>(Hs, Rv[w][0], Rz[w][0], Pi[w][0], dA, HW, c, kq, cok, cb, Vb, Zb);
+      if (dB > 32) tile_product<T, 4>(Hs, Rv[w][1], Rz[w][1], Pi[w][1], dB, HW, c, kq, cok, cb, Vb, Zb);
+      else if (dB > 0) tile_product<T, 2>(Hs, Rv[w][1], Rz[w][1], Pi[w][1], dB, HW, c, kq, cok, cb, Vb, Zb);
     }
     __builtin_amdgcn_wave_barrier();
   }
 }
 
 // W[t][c0 + c] += sum of the S slots of t, in slot order
-__global__ void pn_reduce_kernel(const double* __restrict__ Z, int S, int64_t D, double* __restrict__ W, int64_t ldw,
-                                 int c0, int cval) {
+template <class T>
+__global__ void pn_reduce_kernel(const T* __restrict__ Z, int S, int64_t D, T* __restrict__ W, int64_t ldw, int c0,
+                                 int cval) {
   const int64_t n = D * 16;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
     const int c = (int)(e & 15);
     if (c >= cval) continue;
     const int64_t t = e >> 4;
-    double s = 0.0;
+    T s = T(0);
     for (int k = 0; k < S; k++) s += __builtin_nontemporal_load(Z + ((int64_t)k * D + t) * 16 + c);
     W[t * ldw + c0 + c] += s;
   }
@@ -442,6 +468,8 @@ void build_pn_tiles(Model& m) {
   T.pr_xu.upload(pr_xu);
   T.hb_off.upload(hb_off);
   T.hb.upload(hb);
+  std::vector<float> hb32(hb.begin(), hb.end());
+  T.hb32.upload(hb32);
   T.rect.upload(rect);
   T.rblk.upload(rblk);
   T.item0.upload(items);
@@ -452,40 +480,43 @@ void build_pn_tiles(Model& m) {
   T.on = true;
 }
 
-void launch_pn_tiles(const Model& m, int nb, const double* V, int64_t ldv, double* W, int64_t ldw, hipStream_t s,
-                     bool reduce) {
-  const PNTiles& T = m.pn;
-  PNTileArgs a{};
+template <class T>
+void launch_pn_tiles(const Model& m, int nb, const T* V, int64_t ldv, T* W, int64_t ldw, hipStream_t s, bool reduce) {
+  const PNTiles& P = m.pn;
+  PNTileArgs<T> a{};
   a.V = V;
-  a.Z = T.z.as<double>();
+  a.Z = P.z.as<T>();
   a.ns = m.ns;
   a.nneut = m.n_neut;
   a.D = (int)m.dim;
-  a.vrow = (int)(ldv * 8);
-  a.rkp = T.rk[0].as<int>();
-  a.rkn = T.rk[1].as<int>();
-  a.blk_off = T.boff.as<int>();
+  a.vrow = (int)(ldv * sizeof(T));
+  a.rkp = P.rk[0].as<int>();
+  a.rkn = P.rk[1].as<int>();
+  a.blk_off = P.boff.as<int>();
   a.blk_dn = m.dt.blk_dn.as<int>();
-  a.pr_off = T.pr_off.as<int>();
-  a.pr_xu = T.pr_xu.as<int>();
-  a.hb_off = T.hb_off.as<int>();
-  a.hb = T.hb.as<double>();
-  a.rect = T.rect.as<int>();
-  a.rblk = T.rblk.as<int>();
-  a.items = T.item0.as<int4>();
-  a.nitems = (int)T.items;
-  const unsigned grid = (unsigned)((T.items + 7) / 8 * 8);
+  a.pr_off = P.pr_off.as<int>();
+  a.pr_xu = P.pr_xu.as<int>();
+  a.hb_off = P.hb_off.as<int>();
+  a.hb = (sizeof(T) == 8 ? P.hb : P.hb32).as<T>();
+  a.rect = P.rect.as<int>();
+  a.rblk = P.rblk.as<int>();
+  a.items = P.item0.as<int4>();
+  a.nitems = (int)P.items;
+  const unsigned grid = (unsigned)((P.items + 7) / 8 * 8);
+  const size_t shm = (size_t)(P.max_pairs + 1) * (P.max_pairs + 1) * sizeof(T);
   // a wider product reuses the slot buffer per 16 columns, each tile summed into W in turn; with
   // reduce false (one tile) the own-row kernel sums it
   for (int c0 = 0; c0 < nb; c0 += 16) {
     a.c0 = c0;
     a.cval = std::min(16, nb - c0);
-    hipLaunchKernelGGL(pn_tile_kernel, dim3(grid), dim3(256), (size_t)(T.max_pairs + 1) * (T.max_pairs + 1) * 8, s, a);
+    hipLaunchKernelGGL(pn_tile_kernel<T>, dim3(grid), dim3(256), shm, s, a);
     if (reduce || c0 + 16 < nb)
-      hipLaunchKernelGGL(pn_reduce_kernel, dim3(elementwise_grid(m.dim * 16)), dim3(256), 0, s, (const double*)a.Z,
-                         T.S, m.dim, W, ldw, c0, a.cval);
+      hipLaunchKernelGGL(pn_reduce_kernel<T>, dim3(elementwise_grid(m.dim * 16)), dim3(256), 0, s, (const T*)a.Z, P.S,
+                         m.dim, W, ldw, c0, a.cval);
   }
   TRBL_HIP(hipGetLastError());
 }
+template void launch_pn_tiles<double>(const Model&, int, const double*, int64_t, double*, int64_t, hipStream_t, bool);
+template void launch_pn_tiles<float>(const Model&, int, const float*, int64_t, float*, int64_t, hipStream_t, bool);
 
 }  // namespace trbl

@@ -33,7 +33,7 @@ def fp32_bound(absH_absV, nnz):
     return k * u / (1 - k * u) * absH_absV + 1e-30
 
 
-def term_bound(o, idx, V, fp32=False):
+def term_bound(o, idx, V, fp32=False, extra=0):
     """Rounding bound for rows idx of a per-element H V (a kernel that adds, for each row, the k
     generated terms one product at a time, unmerged) against the oracle.
 
@@ -43,7 +43,9 @@ def term_bound(o, idx, V, fp32=False):
             and its product with V by gamma_k S each (merged counts are <= k and |H||V| <= S):
             gamma_{3k+4} S in all.
       FP32: coefficients rounded to FP32 (u32 each) and a k-term FP32 sum, against an FP64
-            reference of the same rounded V: gamma32_{k+2} S (the FP64 parts are far below)."""
+            reference of the same rounded V: gamma32_{k+2} S (the FP64 parts are far below).
+    extra: further additions on a term's rounding chain (the pair-block product sums its terms in
+    blocks of at most 64 pairs, then the n_prot * n_neut slots: extra = n_prot * n_neut + 64)."""
     ptr, col, val = o.rows_generated(idx)
     k = np.diff(ptr).astype(np.float64)
     absV = np.abs(np.asarray(V, dtype=np.float64))
@@ -52,7 +54,7 @@ def term_bound(o, idx, V, fp32=False):
         sl = slice(ptr[r], ptr[r + 1])
         S[r] = np.abs(val[sl]) @ absV[col[sl]]
     if fp32:
-        u, kk, tiny = 2.0 ** -24, k + 2, 1e-30
+        u, kk, tiny = 2.0 ** -24, k + 2 + extra, 1e-30
     else:
-        u, kk, tiny = 2.0 ** -53, 3 * k + 4, 1e-300
+        u, kk, tiny = 2.0 ** -53, 3 * k + 4 + extra, 1e-300
     return (kk * u / (1 - kk * u))[:, None] * S + tiny

@@ -40,14 +40,15 @@ def test_apply_matches_dense_oracle(case):
     V = random_block(100 + seed, o.dim, nb)
     ref = H @ V
     # per-term bound: the FP64 product sums the pn terms of each core pair unmerged
-    bound = term_bound(o, np.arange(o.dim), V)
+    ex = z * n + 64  # slot sum and pair blocks of the pn kernel
+    bound = term_bound(o, np.arange(o.dim), V, extra=ex)
     W = g.apply(torch.from_numpy(V).cuda()).cpu().numpy()
     assert np.all(np.abs(W - ref) <= bound), np.max(np.abs(W - ref) / bound)
-    # mixed precision: FP32 vectors, FP32 coefficients, FP32 accumulation
+    # mixed precision: FP32 vectors, FP32 coefficients, FP32 accumulation (per-term bound, as above)
     V32 = V.astype(np.float32)
     ref32 = H @ V32.astype(np.float64)
     W32 = g.apply(torch.from_numpy(V32).cuda()).cpu().numpy().astype(np.float64)
-    b32 = fp32_bound(np.abs(H) @ np.abs(V32.astype(np.float64)), nnz)
+    b32 = term_bound(o, np.arange(o.dim), V32, fp32=True, extra=ex)
     assert np.all(np.abs(W32 - ref32) <= b32), np.max(np.abs(W32 - ref32) / b32)
 
 
@@ -63,9 +64,9 @@ PATH_CASES = [
 
 @pytest.mark.parametrize("case", PATH_CASES, ids=lambda c: c[0])
 def test_pair_blocks_match_jump_lists(case):
-    """The two FP64 pn kernels (pair blocks on the matrix cores, and the jump-list rows kernel
+    """The two pn kernels (pair blocks on the matrix cores, and the jump-list rows kernel
     selected with TRBL_PN_TILES=0 at set-up) agree within the sum of their rounding bounds, and
-    each matches the oracle."""
+    each matches the oracle, in FP64 and in FP32."""
     name, orbits, z, n, twoM, par, seed, nb = case
     say("case", name)
     tb = random_tbme(orbits, seed)
@@ -85,11 +86,21 @@ def test_pair_blocks_match_jump_lists(case):
     W1 = g.apply(Vt).cpu().numpy()
     W0 = g0.apply(Vt).cpu().numpy()
     idx = np.arange(o.dim)
-    bound = term_bound(o, idx, V)
+    ex = z * n + 64  # slot sum and pair blocks of the pn kernel
+    bound = term_bound(o, idx, V, extra=ex)
     ref = o.apply_rows(V, idx)
     assert np.all(np.abs(W1 - ref) <= bound)
     assert np.all(np.abs(W0 - ref) <= bound)
     assert np.all(np.abs(W1 - W0) <= 2 * bound)
+    # FP32 (mixed-precision) products of both kernels
+    V32 = V.astype(np.float32)
+    V32t = torch.from_numpy(V32).cuda()
+    X1 = g.apply(V32t).cpu().numpy().astype(np.float64)
+    X0 = g0.apply(V32t).cpu().numpy().astype(np.float64)
+    b32 = term_bound(o, idx, V32, fp32=True, extra=ex)
+    ref32 = o.apply_rows(V32.astype(np.float64), idx)
+    assert np.all(np.abs(X1 - ref32) <= b32)
+    assert np.all(np.abs(X0 - ref32) <= b32)
 
 
 def test_apply_deterministic_and_linear():
@@ -117,16 +128,13 @@ def test_apply_full_size_sampled_rows(wname, nrows):
     ref = o.apply_rows(V, idx)
     ptr, col, val = o.rows(idx)
     nnz = int(np.max(np.diff(ptr)))
-    assert np.all(np.abs(W[idx] - ref) <= term_bound(o, idx, V))
+    ex = w.n_prot * w.n_neut + 64  # slot sum and pair blocks of the pn kernel
+    assert np.all(np.abs(W[idx] - ref) <= term_bound(o, idx, V, extra=ex))
     # FP32 path on the same rows
     V32 = V.astype(np.float32)
     W32 = g.apply(torch.from_numpy(V32).cuda()).cpu().numpy().astype(np.float64)
     ref32 = o.apply_rows(V32.astype(np.float64), idx)
-    absHV32 = np.zeros_like(ref)
-    for r in range(len(idx)):
-        sl = slice(ptr[r], ptr[r + 1])
-        absHV32[r] = np.abs(val[sl]) @ np.abs(V32[col[sl]].astype(np.float64))
-    assert np.all(np.abs(W32[idx] - ref32) <= fp32_bound(absHV32, nnz))
+    assert np.all(np.abs(W32[idx] - ref32) <= term_bound(o, idx, V32, fp32=True, extra=ex))
 
 
 def test_apply_pf66_sampled_rows():
