@@ -9,8 +9,8 @@
 
 namespace trbl {
 
-extern template void dispatch_hv<double>(HVArgs<double>&, const HVPlan&, hipStream_t);
-extern template void dispatch_hv<float>(HVArgs<float>&, const HVPlan&, hipStream_t);
+extern template void dispatch_hv<double>(HVArgs<double>&, const HVPlan&, hipStream_t, int);
+extern template void dispatch_hv<float>(HVArgs<float>&, const HVPlan&, hipStream_t, int);
 
 static int pow2ceil(int x) {
   int p = 1;
@@ -191,18 +191,30 @@ static void run_hv(const Model& m, int nb, const void* V, int64_t ldv, void* W, 
   bool own = m.pn.on && (double)m.dim * (double)ldv * sizeof(T) < 4294967296.0;  // 32-bit byte offsets into V
   for (const auto& B : P.bins) own = own && B->mp == 1;
   a.own = own ? 1 : 0;
-  // the pn part goes to the slot buffer; when one 16-column tile covers the product it is written
-  // first and the own-row kernel sums it into W, else it is added by its own pass after the
-  // identical-particle parts
-  const bool fused = own && P.C == 16 && nb <= 16;
+  if (!own) {
+    dispatch_hv<T>(a, P, s, 3);
+    return;
+  }
+  // With the pair blocks: the columns kernel writes the pp part into W on the model's side stream
+  // while the pair-block kernel writes the pn slots; the own-row kernel then adds the nn part and,
+  // when one 16-column tile covers the product, the slots; a wider product adds its slots in a
+  // pass of its own at the end.
+  const PNTiles& pn = m.pn;
+  TRBL_HIP(hipEventRecord(pn.ev[0], s));
+  TRBL_HIP(hipStreamWaitEvent(pn.side, pn.ev[0], 0));
+  a.ppset = 1;
+  dispatch_hv<T>(a, P, pn.side, 2);
+  TRBL_HIP(hipEventRecord(pn.ev[1], pn.side));
+  const bool fused = P.C == 16 && nb <= 16;
   if (fused) {
     launch_pn_tiles<T>(m, nb, static_cast<const T*>(V), ldv, static_cast<T*>(W), ldw, s, false);
-    a.zs = m.pn.S;
+    a.zs = pn.S;
     a.zstride = m.dim * 16;
-    a.zbuf = m.pn.z.p;
+    a.zbuf = pn.z.p;
   }
-  dispatch_hv<T>(a, P, s);
-  if (own && !fused) launch_pn_tiles<T>(m, nb, static_cast<const T*>(V), ldv, static_cast<T*>(W), ldw, s, true);
+  TRBL_HIP(hipStreamWaitEvent(s, pn.ev[1], 0));
+  dispatch_hv<T>(a, P, s, 1);
+  if (!fused) launch_pn_tiles<T>(m, nb, static_cast<const T*>(V), ldv, static_cast<T*>(W), ldw, s, true);
 }
 
 void prepare_hv_plans(const Model& m, int precision, const int* widths, int n) {

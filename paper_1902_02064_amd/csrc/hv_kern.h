@@ -43,6 +43,7 @@ struct HVArgs {
   int dma;               // source rows copied by global->LDS DMA (16-byte aligned rows)
   int own;               // identical-particle parts only (the pn part is added by the pair blocks)
   int zs;                // own-row kernel: slots of the pair-block buffer summed into W (0: none)
+  int ppset;             // columns kernel writes W (instead of adding to it); the own-row kernel then adds
   int64_t zstride;       // elements between slots of that buffer ([slot][D][16] values of type T)
   const void* zbuf;
   int64_t nn_total;
@@ -625,7 +626,7 @@ __global__ __launch_bounds__(NTB) void hv_own_kernel(HVArgs<T> a) {
         T* w = a.W + (r0 + t) * a.ldw + c0 + L::VPC * k;
 #pragma unroll
         for (int j = 0; j < L::VPC; j++)
-          if (L::VPC * k + j < cvalid) w[j] = v[j];
+          if (L::VPC * k + j < cvalid) w[j] = a.ppset ? w[j] + v[j] : v[j];
       }
       return;
     }
@@ -637,7 +638,7 @@ __global__ __launch_bounds__(NTB) void hv_own_kernel(HVArgs<T> a) {
     const int k = t ^ L::rot();
 #pragma unroll
     for (int v = 0; v < L::VPC; v++)
-      if (k * L::VPC + v < cvalid) w[k * L::VPC + v] = acc[t * L::VPC + v];
+      if (k * L::VPC + v < cvalid) w[k * L::VPC + v] = a.ppset ? w[k * L::VPC + v] + acc[t * L::VPC + v] : acc[t * L::VPC + v];
   }
 }
 
@@ -679,9 +680,15 @@ __global__ __launch_bounds__(1024) void hv_cols_kernel(HVArgs<T> a) {
         axpy_row<T, C>(acc, a.pe_val[at], colv + a.pe_col[at] * RS);
       }
       T* w = a.W + (off + (int64_t)p * dn + n) * a.ldw + c0;
+      if (a.ppset) {
 #pragma unroll
-      for (int c = 0; c < C; c++)
-        if (c < cvalid) w[c] += acc[c];
+        for (int c = 0; c < C; c++)
+          if (c < cvalid) w[c] = acc[c];
+      } else {
+#pragma unroll
+        for (int c = 0; c < C; c++)
+          if (c < cvalid) w[c] += acc[c];
+      }
     }
   }
 }
@@ -727,8 +734,9 @@ static void launch_own(const HVArgs<T>& a, const HVBin& B, hipStream_t s) {
 }
 
 template <class T, int C>
-static void dispatch_c(HVArgs<T>& a, const HVPlan& P, hipStream_t s) {
+static void dispatch_c(HVArgs<T>& a, const HVPlan& P, hipStream_t s, int parts) {
   for (const auto& Bp : P.bins) {
+    if (!(parts & 1)) break;
     const HVBin& B = *Bp;
     a.nchunk = B.nchunk;
     a.bin_blocks = B.blocks.as<int>();
@@ -761,6 +769,7 @@ static void dispatch_c(HVArgs<T>& a, const HVPlan& P, hipStream_t s) {
     } else TRBL_ROWS_RB(1024);
 #undef TRBL_ROWS_RB
   }
+  if (!(parts & 2)) return;
   a.nchunk = P.nchunk_c;
   a.ntile = P.ntile_c;
   if (P.Cc == C) dispatch_cols<T, C>(a, P, s);
@@ -772,22 +781,22 @@ static void dispatch_c(HVArgs<T>& a, const HVPlan& P, hipStream_t s) {
   a.ntile = P.ntile;
 }
 
-// All launches of one block H.V (rows kernel per bin, then the columns kernel).
+// Launches of one block H.V: parts 1 = the rows (or own-row) kernel per bin, 2 = the columns kernel.
 template <class T>
-void dispatch_hv(HVArgs<T>& a, const HVPlan& P, hipStream_t s) {
+void dispatch_hv(HVArgs<T>& a, const HVPlan& P, hipStream_t s, int parts) {
   if constexpr (sizeof(T) == 8) {
     switch (P.C) {
-      case 2: dispatch_c<T, 2>(a, P, s); break;
-      case 4: dispatch_c<T, 4>(a, P, s); break;
-      case 8: dispatch_c<T, 8>(a, P, s); break;
-      default: dispatch_c<T, 16>(a, P, s); break;
+      case 2: dispatch_c<T, 2>(a, P, s, parts); break;
+      case 4: dispatch_c<T, 4>(a, P, s, parts); break;
+      case 8: dispatch_c<T, 8>(a, P, s, parts); break;
+      default: dispatch_c<T, 16>(a, P, s, parts); break;
     }
   } else {
     switch (P.C) {
-      case 4: dispatch_c<T, 4>(a, P, s); break;
-      case 8: dispatch_c<T, 8>(a, P, s); break;
-      case 16: dispatch_c<T, 16>(a, P, s); break;
-      default: dispatch_c<T, 32>(a, P, s); break;
+      case 4: dispatch_c<T, 4>(a, P, s, parts); break;
+      case 8: dispatch_c<T, 8>(a, P, s, parts); break;
+      case 16: dispatch_c<T, 16>(a, P, s, parts); break;
+      default: dispatch_c<T, 32>(a, P, s, parts); break;
     }
   }
 }

@@ -169,6 +169,16 @@ struct PNTiles {
   DevBuf rect, rblk, item0;  // rectangles (pair block, rblk start), per rectangle and pair the target block
                              // (-1: none), work items (rectangle, proton core, first neutron core, count)
   DevBuf boff;               // block offsets as 32-bit integers
+  hipStream_t side = nullptr;  // the columns kernel runs here beside the pair-block kernel
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  PNTiles() = default;
+  PNTiles(const PNTiles&) = delete;
+  PNTiles& operator=(const PNTiles&) = delete;
+  ~PNTiles() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (side) (void)hipStreamDestroy(side);
+  }
   DevBuf z;                  // slot buffer [S][D][16] of one 16-column tile (FP64, or FP32 in its first half)
 };
 

@@ -477,6 +477,9 @@ void build_pn_tiles(Model& m) {
   for (size_t b = 0; b < m.blocks.size(); b++) boff32[b] = (int)m.blocks[b].off;
   T.boff.upload(boff32);
   T.z.alloc(zbytes);
+  if (!T.side) TRBL_HIP(hipStreamCreateWithFlags(&T.side, hipStreamNonBlocking));
+  for (auto& e : T.ev)
+    if (!e) TRBL_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   T.on = true;
 }
 
