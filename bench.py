@@ -445,7 +445,8 @@ def main():
         traffic = stored_traffic(a.workload)
         roof = {"bound": "alu", "achieved": flops / hv_launch / 1e12, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": flops / hv_launch / 1e12 / PEAK_FP64_TFLOPS, "traffic": traffic,
-                "kernel": ("block H.V, FP64: fly_kernel (single species, generated per element) + two row permutations"
+                "kernel": ("block H.V, FP64: fly_tile_kernel (single species: two-body part as pair blocks on the "
+                           "matrix cores) + fly_finalize_kernel (diagonal and slot sum) + two row permutations"
                            if (w.n_prot == 0) != (w.n_neut == 0) and D > 2048 else
                            "block H.V, FP64: pn_tile_kernel (proton-neutron part, core-pair blocks on the matrix "
                            "cores) + hv_own_kernel (neutron-neutron part and slot sum, one launch per sector-width bin) "

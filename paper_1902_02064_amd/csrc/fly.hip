@@ -245,7 +245,9 @@ static void run_fly(const Model& m, int nb, const void* V, int64_t ldv, void* W,
     a.h = d.fly_h32.as<T>();
     a.e = d.fly_e32.as<T>();
   }
-  if (nb <= 8) {
+  if (m.flyt.on) {  // the two-body part by pair blocks, the diagonal and the mask in its final pass
+    launch_fly_tiles<T>(m, nb, vin, win, mask, s);
+  } else if (nb <= 8) {
     const dim3 grid((unsigned)((D + 255) / 256), 1);
     hipLaunchKernelGGL((fly_kernel<T, 8>), grid, dim3(256), 0, s, a);
   } else {

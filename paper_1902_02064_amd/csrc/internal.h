@@ -182,6 +182,19 @@ struct PNTiles {
   DevBuf z;                  // slot buffer [S][D][16] of one 16-column tile (FP64, or FP32 in its first half)
 };
 
+// The identical-particle part of a single-species space as dense pair blocks (pntile.hip): cores
+// of n - 2 nucleons, pairs (a < b) by (2M, parity), C(n, 2) slots per state.
+struct FlyTiles {
+  bool on = false;
+  int S = 0, zw = 8, max_pairs = 0;
+  int64_t items = 0;
+  DevBuf cw;                         // cores, grouped by (2M, parity)
+  DevBuf pr_off, pr_ab, hb_off, hb, hb32;
+  DevBuf rect;                       // per rectangle: pair block, target sector
+  DevBuf items_buf;                  // per work item: rectangle, first core, count, 0
+  DevBuf z;                          // slot buffer [S][D][zw]
+};
+
 struct MTerm {  // m-scheme two-body term c+_a c+_b c_d c_c (species-local state indices)
   int a, b, c, d;
   double h;
@@ -225,6 +238,7 @@ struct Model {
   int fly_s = 1;     // the occupied species
   int fly_half = 0;  // m-states in the low part of the two-level ranking
   mutable DevBuf fly_buf[2];  // V and W in the internal order (FP32, FP64)
+  mutable FlyTiles flyt;      // its two-body part as dense pair blocks (when the slot buffer fits)
   mutable PNTiles pn;         // pn part as dense pair blocks (when its slot buffer fits)
 };
 
@@ -234,6 +248,10 @@ void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const
 // on-the-fly identical-particle H.V for single-species spaces (fly.hip)
 void build_fly_basis(Model& m);
 void build_fly_terms(Model& m);
+void build_fly_tiles(Model& m);
+// internal-order block product of a single-species space by pair blocks (Vint, Wint packed nb)
+template <class T>
+void launch_fly_tiles(const Model& m, int nb, const T* Vint, T* Wint, const double* mask, hipStream_t s);
 // mask (optional, Table-1 order): rows with mask 0 are set to zero without being generated
 void launch_fly(const Model& m, int precision, int nb, const void* V, int64_t ldv, void* W, int64_t ldw,
                 hipStream_t s, const double* mask = nullptr);

@@ -385,6 +385,7 @@ void build_hamiltonian(Model& m, const double* spe_p, const double* spe_n, const
   // (a,b); the adjoint jump c+_c c+_d c_b c_a applied to g' gives g.
   if (m.fly) {  // identical-particle part generated per element; no pn part in this space
     build_fly_terms(m);
+    build_fly_tiles(m);
     m.has_h = true;
     return;
   }

@@ -50,15 +50,46 @@ def test_fly_matches_dense_oracle(case):
     V = random_block(200 + seed, o.dim, nb)
     ref = H @ V
     W = g.apply(torch.from_numpy(V).cuda()).cpu().numpy()
-    bound = term_bound(o, rows, V)
+    # the pair-block path sums blocks of at most 64 pairs, then the C(n, 2) core slots
+    npart = z + n
+    ex = npart * (npart - 1) // 2 + 64
+    bound = term_bound(o, rows, V, extra=ex)
     say("fp64 max err / bound", np.max(np.abs(W - ref) / bound))
     assert np.all(np.abs(W - ref) <= bound)
     V32 = V.astype(np.float32)
     W32 = g.apply(torch.from_numpy(V32).cuda()).cpu().numpy()
     ref32 = H @ V32.astype(np.float64)
-    b32 = term_bound(o, rows, V32, fp32=True)
+    b32 = term_bound(o, rows, V32, fp32=True, extra=ex)
     say("fp32 max err / bound", np.max(np.abs(W32 - ref32) / b32))
     assert np.all(np.abs(W32 - ref32) <= b32)
+
+
+@pytest.mark.parametrize("case", CASES[:3] + CASES[4:], ids=lambda c: c[0])
+def test_fly_pair_blocks_match_per_element_kernel(case):
+    """The single-species two-body part by pair blocks (the default) and by the per-element kernel
+    (TRBL_PN_TILES=0 at set-up): both within the per-term bound of the oracle, FP64 and FP32."""
+    name, orbits, z, n, twoM, par, seed, nb = case
+    say("fly paths", name)
+    spe = [(-0.8 + 0.5 * k) for k in range(len(orbits))]
+    tb = random_tbme(orbits, seed)
+    g1, o = _forced(orbits, z, n, twoM, tb, spe, par)
+    os.environ["TRBL_PN_TILES"] = "0"
+    try:
+        g0, _ = _forced(orbits, z, n, twoM, tb, spe, par)
+    finally:
+        del os.environ["TRBL_PN_TILES"]
+    H = o.dense()
+    rows = np.arange(o.dim)
+    npart = z + n
+    ex = npart * (npart - 1) // 2 + 64
+    for dt, fp32 in ((np.float64, False), (np.float32, True)):
+        V = random_block(400 + seed, o.dim, nb).astype(dt)
+        ref = H @ V.astype(np.float64)
+        bound = term_bound(o, rows, V, fp32=fp32, extra=ex)
+        Vt = torch.from_numpy(V).cuda()
+        for g in (g0, g1):
+            W = g.apply(Vt).cpu().numpy().astype(np.float64)
+            assert np.all(np.abs(W - ref) <= bound)
 
 
 def test_fly_same_as_staged_path():
@@ -92,7 +123,7 @@ def test_sn112_sampled_rows(sn112):
     rows = np.unique(np.concatenate([[0, 1, g.dim - 2, g.dim - 1],
                                      np.random.default_rng(5).integers(0, g.dim, 300)]))
     ref = o.apply_rows(V, rows)
-    bound = term_bound(o, rows, V)
+    bound = term_bound(o, rows, V, extra=w.n_neut * (w.n_neut - 1) // 2 + 64)
     err = np.abs(W[rows] - ref)
     say("sn112 rows", len(rows), "max err/bound", np.max(err / bound))
     assert np.all(err <= bound)
