@@ -188,7 +188,13 @@ static void run_hv(const Model& m, int nb, const void* V, int64_t ldv, void* W, 
   a.citem0 = P.citem0.as<int64_t>();
   // with the pair-block tables the rows and columns kernels write the identical-particle parts and
   // the pair blocks add the pn part
-  bool own = m.pn.on && (double)m.dim * (double)ldv * sizeof(T) < 4294967296.0;  // 32-bit byte offsets into V
+  // The pair blocks work on 16-column tiles, so narrow products cost nearly as much as 16
+  // columns; below the measured crossover (pf 4+4: FP64 from 5 columns, FP32 from 9, or from 5 at
+  // widths that are not a power of two, where the jump-list kernel stages rows without the DMA)
+  // the jump-list kernel runs instead. TRBL_PN_TILES=2 at set-up takes the pair blocks at every width.
+  const bool pow2 = (nb & (nb - 1)) == 0;
+  const bool wide = sizeof(T) == 8 ? nb >= 5 : (nb >= 9 || (nb >= 5 && !pow2));
+  bool own = m.pn.on && (wide || m.pn.force) && (double)m.dim * (double)ldv * sizeof(T) < 4294967296.0;
   for (const auto& B : P.bins) own = own && B->mp == 1;
   a.own = own ? 1 : 0;
   if (!own) {

@@ -156,6 +156,7 @@ struct HVPlan {
 // of the symmetric block H_M[(x,u)][(y,v)] restricted to the pairs outside the cores.
 struct PNTiles {
   bool on = false;
+  bool force = false;        // at every product width (TRBL_PN_TILES=2), not only the wide ones
   int S = 0;                 // contribution slots per basis state: n_prot * n_neut
   int nk = 0;                // pair blocks (2M of a pair from -2 tjmax to 2 tjmax)
   int nrect = 0;             // core-group rectangles (fixed core 2M and parity on both sides)

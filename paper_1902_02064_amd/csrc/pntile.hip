@@ -560,6 +560,7 @@ void build_pn_tiles(Model& m) {
   T.z.release();
   const char* env = std::getenv("TRBL_PN_TILES");
   if (env && env[0] == '0') return;
+  T.force = env && env[0] == '2';
   if (m.fly || m.n_prot == 0 || m.n_neut == 0) return;
   const int ns = m.ns, tj = m.cl.tjmax;
   const int nk = 2 * tj + 1;

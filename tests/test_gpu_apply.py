@@ -53,12 +53,14 @@ def test_apply_matches_dense_oracle(case):
 
 
 PATH_CASES = [
-    # name, orbits, Z, N, 2M, parity, seed, nb: the FP64 pn part by core-pair blocks (one 16-column
+    # name, orbits, Z, N, 2M, parity, seed, nb: the pn part by core-pair blocks (one 16-column
     # tile summed by the own-row kernel, several tiles, narrower tiles) against the jump-list kernel
     ("pf22_nb16", PF_ORBITS, 2, 2, 0, 0, 4, 16),
     ("pf31_nb40", PF_ORBITS, 3, 1, 0, 0, 5, 40),
     ("sd32_odd_nb5", SD_ORBITS, 3, 2, 1, 0, 2, 5),
     ("mixpar_neg_nb12", MIXED_PAR, 2, 1, 1, -1, 7, 12),
+    ("sd22_nb1", SD_ORBITS, 2, 2, 0, 0, 8, 1),
+    ("pf22_nb3", PF_ORBITS, 2, 2, 2, 0, 9, 3),
 ]
 
 
@@ -71,10 +73,11 @@ def test_pair_blocks_match_jump_lists(case):
     say("case", name)
     tb = random_tbme(orbits, seed)
     spe = [(-1.5 + 0.7 * k) for k in range(len(orbits))]
-    g, o = pair(orbits, z, n, twoM, tb, spe, spe, par)
     old = os.environ.get("TRBL_PN_TILES")
-    os.environ["TRBL_PN_TILES"] = "0"
     try:
+        os.environ["TRBL_PN_TILES"] = "2"  # pair blocks at every width
+        g, o = pair(orbits, z, n, twoM, tb, spe, spe, par)
+        os.environ["TRBL_PN_TILES"] = "0"  # jump lists
         g0, _ = pair(orbits, z, n, twoM, tb, spe, spe, par, oracle=False)
     finally:
         if old is None:
