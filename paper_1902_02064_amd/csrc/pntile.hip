@@ -860,6 +860,12 @@ void build_fly_tiles(Model& m) {
       if (itk != kid.end()) rs.push_back({itk->second, sv.second});
     }
     if (rs.empty()) continue;
+    // cores in the order of the internal numbering (low part of the m-states first): consecutive
+    // cores then reach targets and sources in nearby ranges of V and of the slots
+    const uint64_t lm = (1ull << m.fly_half) - 1;
+    std::sort(kv.second.begin(), kv.second.end(), [&](uint64_t x, uint64_t y) {
+      return (x & lm) != (y & lm) ? (x & lm) < (y & lm) : (x >> m.fly_half) < (y >> m.fly_half);
+    });
     const int c0 = (int)cw.size();
     cw.insert(cw.end(), kv.second.begin(), kv.second.end());
     const int n = (int)kv.second.size();
