@@ -88,7 +88,7 @@ def stored_nnz(name):
     return None
 
 
-HV_SOURCES = ("hv.hip", "hv_kern.h", "hv_f64.hip", "hv_f32.hip", "pntile.hip")
+HV_SOURCES = ("hv.hip", "hv_kern.h", "hv_f64.hip", "hv_f32.hip", "pntile.hip", "tilecore.h")
 
 
 def hv_source_digest():

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtrbl.so")
-SOURCES = ["model.cpp", "abi.cpp", "solver.cpp", "hv.hip", "hv_f64.hip", "hv_f32.hip", "dense.hip", "eig.hip", "grad.hip", "fly.hip", "jumps.hip", "pntile.hip"]
+SOURCES = ["model.cpp", "abi.cpp", "solver.cpp", "hv.hip", "hv_f64.hip", "hv_f32.hip", "dense.hip", "eig.hip", "grad.hip", "fly.hip", "jumps.hip", "pntile.hip", "flytile.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
