@@ -245,7 +245,9 @@ static void run_fly(const Model& m, int nb, const void* V, int64_t ldv, void* W,
     a.h = d.fly_h32.as<T>();
     a.e = d.fly_e32.as<T>();
   }
-  if (m.flyt.on) {  // the two-body part by pair blocks, the diagonal and the mask in its final pass
+  // the two-body part by pair blocks (the diagonal in its final pass); products restricted to a
+  // truncated space keep the per-element kernel, which does not generate the rows outside it
+  if (m.flyt.on && !mask) {
     launch_fly_tiles<T>(m, nb, vin, win, mask, s);
   } else if (nb <= 8) {
     const dim3 grid((unsigned)((D + 255) / 256), 1);
