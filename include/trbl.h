@@ -147,14 +147,22 @@ int trbl_random_tbme(const trbl_orbit* orbits, int n_orbits, uint64_t seed, doub
 
 /* Set H = sum_a e_a n_a + two-body (Sec. 2). spe_p, spe_n: one energy per orbit (host).
    tbme: n_v host elements. Copies everything, builds the one-body jump and
-   identical-particle tables of App. B on the device. */
+   identical-particle tables of App. B on the device. Where it fits in a quarter of the free
+   device memory (and below 4 GiB for two species), it also builds the core-pair blocks of the
+   matrix-core products and their slot buffer, which the model keeps:
+   n_prot * n_neut * D * 16 doubles for the pn part of two species, and
+   C(n, 2) * D * 8 doubles for n nucleons of one species. Setting TRBL_PN_TILES=0 in the
+   environment before this call keeps the jump-list and per-element kernels only. */
 int trbl_set_hamiltonian(trbl_model* m, const double* spe_p, const double* spe_n, const trbl_tbme* tbme,
                          int64_t n_v);
 
 /* W = H V for a block of nb vectors (App. B, on-the-fly block H.V). V, W: device [D][nb],
    FP64 if precision == TRBL_FP64, FP32 (FP32 accumulation) if TRBL_MIXED. V and W must not alias.
-   For single-species spaces generated per element the model's work blocks are used, so products
-   (and solves) of one such model must not overlap on different streams. */
+   Products use the model's own work memory: the slot buffer of the core-pair blocks, and the
+   work blocks of single-species spaces generated per element. Products and solves of one model
+   therefore must not overlap on different streams. With two species, the proton-proton part
+   runs on a second stream that the model owns; it waits for the work already queued on
+   `stream`, and `stream` waits for it before the call returns, so the caller sees one stream. */
 int trbl_apply(const trbl_model* m, int precision, int nb, const void* V, void* W, void* stream);
 
 /* Lowest n_eig eigenpairs by TRBL (Alg. 4, Sec. 3.4). evals: host n_eig doubles (ascending).

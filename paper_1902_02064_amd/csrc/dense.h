@@ -22,14 +22,16 @@ template <class TA, class TB>
 void tn(const TA* A, int64_t lda, int m, const TB* B, int64_t ldb, int nb, int64_t D, double* C, Scratch& s,
         hipStream_t st);
 // Bout = Bin - A C; mode 1 also forms A^T Bout into Pout, mode 2 keeps Bout^T Bout partials in s
-// (of the stored values; FP32 Bout: modes 0 and 2 only).
+// (of the stored values; FP32 Bout: modes 0 and 2 only). Modes 0 and 2 may store the same
+// values a second time into Bout2 (leading dimension ldo2).
 template <class TA, class TI, class TO = double>
 void update(const TA* A, int64_t lda, int m, const double* C, const TI* Bin, int64_t ldi, TO* Bout, int64_t ldo,
-            int nb, int64_t D, int mode, double* Pout, Scratch& s, hipStream_t st);
-// Bout = Bin R (R nb x nb); gram keeps Bout^T Bout partials in s.
+            int nb, int64_t D, int mode, double* Pout, Scratch& s, hipStream_t st, TO* Bout2 = nullptr,
+            int64_t ldo2 = 0);
+// Bout = Bin R (R nb x nb); gram keeps Bout^T Bout partials in s; optional second copy in Bout2.
 template <class TI, class TO>
 void apply_small(const TI* Bin, int64_t ldi, const double* R, TO* Bout, int64_t ldo, int nb, int64_t D, bool gram,
-                 Scratch& s, hipStream_t st);
+                 Scratch& s, hipStream_t st, TO* Bout2 = nullptr, int64_t ldo2 = 0);
 // Cholesky of the sum of G partial nb x nb Gram matrices: R, R^-1, beta = R Rprev (if beta), status.
 void chol(const double* part, int G, int nb, double* R, double* Rinv, const double* Rprev, double* beta, int* status,
           hipStream_t st);

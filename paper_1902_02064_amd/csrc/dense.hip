@@ -164,7 +164,7 @@ template <class TA, class TI, class TO, int WAVES, int MAXI, int MAXC>
 __global__ __launch_bounds__(WAVES * 64) void update_kernel(const TA* __restrict__ A, int64_t lda, int m,
                                                      const double* __restrict__ C, const TI* Bin, int64_t ldi,
                                                      TO* Bout, int64_t ldo, int nb, int64_t D, int mode,
-                                                     double* __restrict__ part) {
+                                                     double* __restrict__ part, TO* Bout2, int64_t ldo2) {
   constexpr int ROWS = WAVES * 16;
   extern __shared__ double lds[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -219,6 +219,7 @@ __global__ __launch_bounds__(WAVES * 64) void update_kernel(const TA* __restrict
         if (r < D && c < nb) {
           const TO out = (TO)(Bin ? ld(Bin + r * ldi + c) - acc[q][v] : acc[q][v]);
           Bout[r * ldo + c] = out;
+          if (Bout2) Bout2[r * ldo2 + c] = out;
           val = (double)out;
         }
         Wt[rl * nbp + c] = val;
@@ -781,8 +782,9 @@ void tn(const TA* A, int64_t lda, int m, const TB* B, int64_t ldb, int nb, int64
 
 template <class TA, class TI, class TO>
 void update(const TA* A, int64_t lda, int m, const double* C, const TI* Bin, int64_t ldi, TO* Bout, int64_t ldo,
-            int nb, int64_t D, int mode, double* Pout, Scratch& s, hipStream_t st) {
+            int nb, int64_t D, int mode, double* Pout, Scratch& s, hipStream_t st, TO* Bout2, int64_t ldo2) {
   TRBL_REQUIRE(m >= 1 && m <= 768 && nb >= 1 && nb <= 64, TRBL_E_INVALID, "projection shape out of range");
+  TRBL_REQUIRE(!Bout2 || (mode != 1 && Bout2 != Bout), TRBL_E_INVALID, "second output only for modes 0 and 2");
   const int mt = (m + 15) / 16, ct = (nb + 15) / 16, npan = (m + 63) / 64;
   if constexpr (sizeof(TO) == 8) {
   if (mode == 1 && mt <= 32 && ct == 1 && Bin) {  // one pass over A for the update and the projection
@@ -811,7 +813,7 @@ void update(const TA* A, int64_t lda, int m, const double* C, const TI* Bin, int
     // from Bin, the rest in place on Bout; the fused products after the last chunk (Gram) or
     // separately (A^T Bout)
     const int mmax = (int)((160 * 1024 / sizeof(double) - 4 * 16 * ct * 16) / (ct * 16)) / 16 * 16;
-    TRBL_REQUIRE(mmax >= 16 && Bin != nullptr, TRBL_E_INVALID, "update tile does not fit in LDS");
+    TRBL_REQUIRE(mmax >= 16 && Bin != nullptr && !Bout2, TRBL_E_INVALID, "update tile does not fit in LDS");
     for (int k0 = 0; k0 < m; k0 += mmax) {
       const int mc = std::min(mmax, m - k0);
       const bool last = k0 + mc >= m;
@@ -836,7 +838,7 @@ void update(const TA* A, int64_t lda, int m, const double* C, const TI* Bin, int
   const int mi = (npan + waves - 1) / waves;  // 64-column panels per wave (mode 1)
 #define UPD_LAUNCH(W, MI, MC)                                                                                     \
   hipLaunchKernelGGL((update_kernel<TA, TI, TO, W, MI, MC>), dim3(G), dim3(W * 64), shm, st, A, lda, m, C, Bin, ldi, \
-                     Bout, ldo, nb, D, mode, part)
+                     Bout, ldo, nb, D, mode, part, Bout2, ldo2)
   if (waves == 8) {
     if (ct == 1) {
       if (mi <= 1) UPD_LAUNCH(8, 1, 1);
@@ -865,12 +867,13 @@ void update(const TA* A, int64_t lda, int m, const double* C, const TI* Bin, int
 
 template <class TI, class TO>
 void apply_small(const TI* Bin, int64_t ldi, const double* R, TO* Bout, int64_t ldo, int nb, int64_t D, bool gram,
-                 Scratch& s, hipStream_t st) {
+                 Scratch& s, hipStream_t st, TO* Bout2, int64_t ldo2) {
   if constexpr (sizeof(TO) == 8 || sizeof(TI) == sizeof(TO)) {
     // FP64 output, or FP32 in and out: the MFMA row-streaming kernel, Bout = Bin R (+ Gram)
-    update<TI, TI, TO>(Bin, ldi, nb, R, nullptr, 0, Bout, ldo, nb, D, gram ? 2 : 0, nullptr, s, st);
+    update<TI, TI, TO>(Bin, ldi, nb, R, nullptr, 0, Bout, ldo, nb, D, gram ? 2 : 0, nullptr, s, st, Bout2, ldo2);
     return;
   }
+  TRBL_REQUIRE(!Bout2, TRBL_E_INVALID, "second output only for FP64 or same-precision products");
   const int rows = 2048 / nb;
   const int G = grid_for(D, rows * 4, 1024);
   double* part = gram ? s.partials((size_t)G * nb * nb) : nullptr;
@@ -1005,21 +1008,24 @@ template void tn<float, double>(const float*, int64_t, int, const double*, int64
 template void tn<double, float>(const double*, int64_t, int, const float*, int64_t, int, int64_t, double*, Scratch&,
                                 hipStream_t);
 template void update<double, double, double>(const double*, int64_t, int, const double*, const double*, int64_t,
-                                             double*, int64_t, int, int64_t, int, double*, Scratch&, hipStream_t);
+                                             double*, int64_t, int, int64_t, int, double*,
+                                             Scratch&, hipStream_t, double*, int64_t);
 template void update<float, float, double>(const float*, int64_t, int, const double*, const float*, int64_t, double*,
-                                           int64_t, int, int64_t, int, double*, Scratch&, hipStream_t);
+                                           int64_t, int, int64_t, int, double*,
+                                           Scratch&, hipStream_t, double*, int64_t);
 template void update<float, double, double>(const float*, int64_t, int, const double*, const double*, int64_t,
-                                            double*, int64_t, int, int64_t, int, double*, Scratch&, hipStream_t);
+                                            double*, int64_t, int, int64_t, int, double*,
+                                            Scratch&, hipStream_t, double*, int64_t);
 template void update<float, float, float>(const float*, int64_t, int, const double*, const float*, int64_t, float*,
-                                          int64_t, int, int64_t, int, double*, Scratch&, hipStream_t);
+                                          int64_t, int, int64_t, int, double*, Scratch&, hipStream_t, float*, int64_t);
 template void apply_small<double, double>(const double*, int64_t, const double*, double*, int64_t, int, int64_t, bool,
-                                          Scratch&, hipStream_t);
+                                          Scratch&, hipStream_t, double*, int64_t);
 template void apply_small<double, float>(const double*, int64_t, const double*, float*, int64_t, int, int64_t, bool,
-                                         Scratch&, hipStream_t);
+                                         Scratch&, hipStream_t, float*, int64_t);
 template void apply_small<float, float>(const float*, int64_t, const double*, float*, int64_t, int, int64_t, bool,
-                                        Scratch&, hipStream_t);
+                                        Scratch&, hipStream_t, float*, int64_t);
 template void apply_small<float, double>(const float*, int64_t, const double*, double*, int64_t, int, int64_t, bool,
-                                         Scratch&, hipStream_t);
+                                         Scratch&, hipStream_t, double*, int64_t);
 template void rowgemm<double, double>(const double*, int64_t, int, const double*, int64_t, int, double*, int64_t,
                                       int64_t, int, int, int, hipStream_t, double*, int64_t);
 template void rowgemm<float, float>(const float*, int64_t, int, const double*, int64_t, int, float*, int64_t, int64_t,

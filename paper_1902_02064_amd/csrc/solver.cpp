@@ -227,11 +227,13 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
   double r_prev = -1.0;
   std::vector<double> th_prev;  // Ritz values at the previous test (Ritz-change criterion)
   int nchk = 0;
+  bool vk_current = false;  // Vk already holds the basis block at column c0 (stored there by the QR)
   for (it = 1; it <= o.max_iter; it++) {
     k++;
     const int c0 = kx + (k - 1) * nb;
     mcur = c0 + nb;
-    copy_cols<TQ, TQ>(Q + c0, ldq, Vk, nb, D, nb, st);
+    if (!vk_current) copy_cols<TQ, TQ>(Q + c0, ldq, Vk, nb, D, nb, st);
+    vk_current = false;
     TRBL_HIP(hipEventRecord(ev.e[0], st));
     // W := H V_k (mixed: in the basis array's next block, Wq)
     float* Wq = mixed ? reinterpret_cast<float*>(Q) + mcur : nullptr;
@@ -269,21 +271,24 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
     TRBL_HIP(hipEventRecord(ev.e[2], st));
     // V_{k+1} beta_k := QR(W): Cholesky QR twice
     chol(sc.last_part, sc.last_G, nb, R1, R1i, nullptr, nullptr, status, st);
+    // the second factor's product also stores the new block packed into Vk, the H.V input of the
+    // next iteration
     if (mixed) {
       apply_small<float, float>(Wq, ldq, R1i, Wq, ldq, nb, D, true, sc, st);
       chol(sc.last_part, sc.last_G, nb, R2, R2i, R1, beta, status + 1, st);
-      apply_small<float, float>(Wq, ldq, R2i, Wq, ldq, nb, D, false, sc, st);
+      apply_small<float, float>(Wq, ldq, R2i, Wq, ldq, nb, D, false, sc, st, reinterpret_cast<float*>(Vk), nb);
     } else {
       apply_small<double, double>(W, nb, R1i, W, nb, nb, D, true, sc, st);
       chol(sc.last_part, sc.last_G, nb, R2, R2i, R1, beta, status + 1, st);
-      apply_small<double, TQ>(W, nb, R2i, Q + mcur, ldq, nb, D, false, sc, st);
+      apply_small<double, TQ>(W, nb, R2i, Q + mcur, ldq, nb, D, false, sc, st, Vk, nb);
     }
     t_beta(T, lm, c0, mcur, nb, beta, st);
     TRBL_HIP(hipMemcpyAsync(sth, status, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
     TRBL_HIP(hipStreamSynchronize(st));
     if (sth[0] || sth[1]) {
       // breakdown: W was scaled in place; form it again (same arithmetic) and take the
-      // column-wise QR with replacement
+      // column-wise QR with replacement (Vk already holds the rejected block: V_k again first)
+      copy_cols<TQ, TQ>(Q + c0, ldq, Vk, nb, D, nb, st);
       if (mixed) {
         W = w64();
         apply_h(TRBL_MIXED, nb, Vk, nb, Wq, ldq);
@@ -301,6 +306,8 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
       robust_qr(W, mcur, (uint64_t)it);
       t_beta(T, lm, c0, mcur, nb, beta, st);
       sth[0] = sth[1] = 0;
+    } else {
+      vk_current = true;
     }
     TRBL_HIP(hipEventRecord(ev.e[3], st));
     // diagonalise T^(k) (every check_every iterations and before every restart)
@@ -383,6 +390,7 @@ static int solve_t(const Model& m, const trbl_opts& o, double* evals, void* evec
       kx = ls;
       k = 0;
       restarts++;
+      vk_current = false;  // the restart product may use Vk as its work buffer
     }
   }
   if (it > o.max_iter) it = o.max_iter;
