@@ -126,6 +126,22 @@ def test_krylov_exhaustion_small_space():
     assert np.abs(ev - e[:3]).max() <= 1e-9 * max(1.0, np.abs(e).max())
 
 
+def test_breakdown_inside_iteration(sd22):
+    """Start block = one exact eigenvector of H and one random vector: after the orthogonalisation
+    of H V_1 its first column is rounding noise, so the Cholesky QR of the first new block fails
+    inside the iteration. The product H V_k is then formed again from the current block (which
+    the QR's last product had already overwritten in the packed H.V input), and the column-wise
+    QR replaces the deficient column. The solve must still give numpy's lowest eigenvalues."""
+    w, g, o, H, e = sd22
+    X = np.linalg.eigh(H)[1]
+    v0 = np.stack([X[:, 4], random_block(7, g.dim, 1)[:, 0]], axis=1).copy()
+    say("sd22 start block with an eigenvector")
+    ev, _, info = g.solve(2, 6, 12, 40, 1e-9, "fp64", v0=torch.from_numpy(v0).cuda())
+    say("breakdowns", info.breakdowns, "iterations", info.iterations, "ev", ev[:3], "exact", e[:3])
+    assert info.converged and info.breakdowns >= 1
+    assert np.abs(ev - e[:6]).max() <= 1e-9 * np.abs(e).max()
+
+
 @pytest.mark.parametrize("every", [1, 3, -1])
 def test_check_schedules_agree(sd22, every):
     """Convergence tested every iteration, every 3rd, or on the adaptive schedule: same eigenpairs."""
