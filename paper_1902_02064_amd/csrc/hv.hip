@@ -9,8 +9,8 @@
 
 namespace trbl {
 
-extern template void dispatch_hv<double>(HVArgs<double>&, const HVPlan&, hipStream_t, int);
-extern template void dispatch_hv<float>(HVArgs<float>&, const HVPlan&, hipStream_t, int);
+extern template void dispatch_hv<double>(HVArgs<double>&, const HVPlan&, hipStream_t, int, unsigned);
+extern template void dispatch_hv<float>(HVArgs<float>&, const HVPlan&, hipStream_t, int, unsigned);
 
 static int pow2ceil(int x) {
   int p = 1;
@@ -198,7 +198,7 @@ static void run_hv(const Model& m, int nb, const void* V, int64_t ldv, void* W, 
   for (const auto& B : P.bins) own = own && B->mp == 1;
   a.own = own ? 1 : 0;
   if (!own) {
-    dispatch_hv<T>(a, P, s, 3);
+    dispatch_hv<T>(a, P, s, 3, ~0u);
     return;
   }
   // With the pair blocks: the columns kernel writes the pp part into W on the model's side stream
@@ -209,7 +209,7 @@ static void run_hv(const Model& m, int nb, const void* V, int64_t ldv, void* W, 
   TRBL_HIP(hipEventRecord(pn.ev[0], s));
   TRBL_HIP(hipStreamWaitEvent(pn.side, pn.ev[0], 0));
   a.ppset = 1;
-  dispatch_hv<T>(a, P, pn.side, 2);
+  dispatch_hv<T>(a, P, pn.side, 2, ~0u);
   TRBL_HIP(hipEventRecord(pn.ev[1], pn.side));
   const bool fused = P.C == 16 && nb <= 16;
   if (fused) {
@@ -218,8 +218,20 @@ static void run_hv(const Model& m, int nb, const void* V, int64_t ldv, void* W, 
     a.zstride = m.dim * 16;
     a.zbuf = pn.z.p;
   }
+  // the own-row bins write disjoint rows: the largest runs here, the others on the side stream
+  // (after the columns kernel there, and after the pair blocks)
+  TRBL_REQUIRE(P.bins.size() <= 32, TRBL_E_INVALID, "more own-row bins than the stream split takes");
+  size_t big = 0;
+  for (size_t i = 1; i < P.bins.size(); i++)
+    if (P.bins[i]->items * P.bins[i]->nthr > P.bins[big]->items * P.bins[big]->nthr) big = i;
+  const unsigned bigmask = 1u << big;
+  TRBL_HIP(hipEventRecord(pn.ev[2], s));
+  TRBL_HIP(hipStreamWaitEvent(pn.side, pn.ev[2], 0));
+  dispatch_hv<T>(a, P, pn.side, 1, ~bigmask);
+  TRBL_HIP(hipEventRecord(pn.ev[3], pn.side));
   TRBL_HIP(hipStreamWaitEvent(s, pn.ev[1], 0));
-  dispatch_hv<T>(a, P, s, 1);
+  dispatch_hv<T>(a, P, s, 1, bigmask);
+  TRBL_HIP(hipStreamWaitEvent(s, pn.ev[3], 0));
   if (!fused) launch_pn_tiles<T>(m, nb, static_cast<const T*>(V), ldv, static_cast<T*>(W), ldw, s, true);
 }
 

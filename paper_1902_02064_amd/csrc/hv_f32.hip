@@ -2,5 +2,5 @@
 #include "hv_kern.h"
 
 namespace trbl {
-template void dispatch_hv<float>(HVArgs<float>&, const HVPlan&, hipStream_t, int);
+template void dispatch_hv<float>(HVArgs<float>&, const HVPlan&, hipStream_t, int, unsigned);
 }  // namespace trbl

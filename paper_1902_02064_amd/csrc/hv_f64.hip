@@ -2,5 +2,5 @@
 #include "hv_kern.h"
 
 namespace trbl {
-template void dispatch_hv<double>(HVArgs<double>&, const HVPlan&, hipStream_t, int);
+template void dispatch_hv<double>(HVArgs<double>&, const HVPlan&, hipStream_t, int, unsigned);
 }  // namespace trbl

@@ -734,10 +734,11 @@ static void launch_own(const HVArgs<T>& a, const HVBin& B, hipStream_t s) {
 }
 
 template <class T, int C>
-static void dispatch_c(HVArgs<T>& a, const HVPlan& P, hipStream_t s, int parts) {
-  for (const auto& Bp : P.bins) {
+static void dispatch_c(HVArgs<T>& a, const HVPlan& P, hipStream_t s, int parts, unsigned binmask) {
+  for (size_t bi = 0; bi < P.bins.size(); bi++) {
     if (!(parts & 1)) break;
-    const HVBin& B = *Bp;
+    if (!((binmask >> bi) & 1)) continue;
+    const HVBin& B = *P.bins[bi];
     a.nchunk = B.nchunk;
     a.bin_blocks = B.blocks.as<int>();
     a.bin_item0 = B.item0.as<int64_t>();
@@ -783,20 +784,20 @@ static void dispatch_c(HVArgs<T>& a, const HVPlan& P, hipStream_t s, int parts) 
 
 // Launches of one block H.V: parts 1 = the rows (or own-row) kernel per bin, 2 = the columns kernel.
 template <class T>
-void dispatch_hv(HVArgs<T>& a, const HVPlan& P, hipStream_t s, int parts) {
+void dispatch_hv(HVArgs<T>& a, const HVPlan& P, hipStream_t s, int parts, unsigned binmask) {
   if constexpr (sizeof(T) == 8) {
     switch (P.C) {
-      case 2: dispatch_c<T, 2>(a, P, s, parts); break;
-      case 4: dispatch_c<T, 4>(a, P, s, parts); break;
-      case 8: dispatch_c<T, 8>(a, P, s, parts); break;
-      default: dispatch_c<T, 16>(a, P, s, parts); break;
+      case 2: dispatch_c<T, 2>(a, P, s, parts, binmask); break;
+      case 4: dispatch_c<T, 4>(a, P, s, parts, binmask); break;
+      case 8: dispatch_c<T, 8>(a, P, s, parts, binmask); break;
+      default: dispatch_c<T, 16>(a, P, s, parts, binmask); break;
     }
   } else {
     switch (P.C) {
-      case 4: dispatch_c<T, 4>(a, P, s, parts); break;
-      case 8: dispatch_c<T, 8>(a, P, s, parts); break;
-      case 16: dispatch_c<T, 16>(a, P, s, parts); break;
-      default: dispatch_c<T, 32>(a, P, s, parts); break;
+      case 4: dispatch_c<T, 4>(a, P, s, parts, binmask); break;
+      case 8: dispatch_c<T, 8>(a, P, s, parts, binmask); break;
+      case 16: dispatch_c<T, 16>(a, P, s, parts, binmask); break;
+      default: dispatch_c<T, 32>(a, P, s, parts, binmask); break;
     }
   }
 }

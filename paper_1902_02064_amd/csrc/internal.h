@@ -170,8 +170,8 @@ struct PNTiles {
   DevBuf rect, rblk, item0;  // rectangles (pair block, rblk start), per rectangle and pair the target block
                              // (-1: none), work items (rectangle, proton core, first neutron core, count)
   DevBuf boff;               // block offsets as 32-bit integers
-  hipStream_t side = nullptr;  // the columns kernel runs here beside the pair-block kernel
-  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipStream_t side = nullptr;  // the columns kernel and the smaller own-row bins run here
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   PNTiles() = default;
   PNTiles(const PNTiles&) = delete;
   PNTiles& operator=(const PNTiles&) = delete;
