@@ -160,9 +160,10 @@ int trbl_set_hamiltonian(trbl_model* m, const double* spe_p, const double* spe_n
    FP64 if precision == TRBL_FP64, FP32 (FP32 accumulation) if TRBL_MIXED. V and W must not alias.
    Products use the model's own work memory: the slot buffer of the core-pair blocks, and the
    work blocks of single-species spaces generated per element. Products and solves of one model
-   therefore must not overlap on different streams. With two species, the proton-proton part
-   runs on a second stream that the model owns; it waits for the work already queued on
-   `stream`, and `stream` waits for it before the call returns, so the caller sees one stream. */
+   therefore must not overlap on different streams. With the core-pair blocks, part of the
+   product (the proton-proton part, the smaller neutron-sector bins) runs on a second stream that
+   the model owns; that work waits for the work already queued on `stream`, and `stream` waits
+   for it before the call returns, so the caller sees one stream. */
 int trbl_apply(const trbl_model* m, int precision, int nb, const void* V, void* W, void* stream);
 
 /* Lowest n_eig eigenpairs by TRBL (Alg. 4, Sec. 3.4). evals: host n_eig doubles (ascending).
