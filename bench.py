@@ -450,7 +450,10 @@ def main():
                            if (w.n_prot == 0) != (w.n_neut == 0) and D > 2048 else
                            "block H.V, FP64: pn_tile_kernel (proton-neutron part, core-pair blocks on the matrix "
                            "cores) + hv_own_kernel (neutron-neutron part and slot sum, one launch per sector-width bin) "
-                           "+ hv_cols_kernel (proton-proton part)"),
+                           "+ hv_cols_kernel (proton-proton part)"
+                           if a.workload == "pf44" else
+                           "block H.V, FP64: every kernel of one product (the proton-neutron part on core-pair blocks "
+                           "or on jump lists, as chosen at set-up from the width and the pairs per core pair)"),
                 "measured_GBs": (traffic / hv_launch / 1e9) if traffic else None,
                 "per_launch": {"elements": nnz, "flops": flops, "compulsory_bytes": bytes_min,
                                "avg_duration_s": hv_launch}}

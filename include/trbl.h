@@ -148,8 +148,9 @@ int trbl_random_tbme(const trbl_orbit* orbits, int n_orbits, uint64_t seed, doub
 /* Set H = sum_a e_a n_a + two-body (Sec. 2). spe_p, spe_n: one energy per orbit (host).
    tbme: n_v host elements. Copies everything, builds the one-body jump and
    identical-particle tables of App. B on the device. Where it fits in a quarter of the free
-   device memory (and below 4 GiB for two species), it also builds the core-pair blocks of the
-   matrix-core products and their slot buffer, which the model keeps:
+   device memory (and below 4 GiB for two species), and for two species where a core pair
+   carries on average at least 16 source pairs (pf-shell spaces; not sd), it also builds the
+   core-pair blocks of the matrix-core products and their slot buffer, which the model keeps:
    n_prot * n_neut * D * 16 doubles for the pn part of two species, and
    C(n, 2) * D * 8 doubles for n nucleons of one species. Setting TRBL_PN_TILES=0 in the
    environment before this call keeps the jump-list and per-element kernels only. */
