@@ -275,10 +275,10 @@ void build_pn_tiles(Model& m) {
   // Every slot row (16 values written, then read back) carries the products of one core pair:
   // on average about L = (pair-weighted mean block size) x (share of the proton states outside a
   // proton core) x (the same for neutrons) source pairs. With few of them the slot traffic costs
-  // more than the elements it carries: pf 3+3, 4+4 and 5+3 (L = 31 to 35) run 1.1 to 2.1 times
-  // faster on the pair blocks, sd 5+5 and 6+6 (L = 9.0 and 6.9) up to 2.8 times slower, sd 4+4
-  // (L = 11.4) slower at 8 columns and faster at 16. The pair blocks are taken from L = 16 on
-  // (TRBL_PN_TILES=2 takes them regardless).
+  // more than the elements it carries: pf 3+3, 4+4 and 5+3 (L = 31 to 35) run 1.0 to 2.3 times
+  // faster on the pair blocks (FP64 at 8 and 16 columns, FP32 at 16), sd 5+5 and 6+6 (L = 9.0
+  // and 6.9) up to 2.9 times slower, sd 4+4 (L = 11.4) slower at 8 columns and faster at 16. The
+  // pair blocks are taken from L = 16 on (TRBL_PN_TILES=2 takes them regardless).
   {
     double n1 = 0.0, n2 = 0.0;
     for (auto& v : pairs) {
